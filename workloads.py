@@ -1,0 +1,240 @@
+"""Seeded synthetic inputs for the constant-OPL ray march.
+
+This module only *draws data*: medium parameters, index grids and ray launch
+states.  It contains none of the ray-tracing arithmetic (no index evaluation,
+no refraction, no stepping), so that the FP64 CPU oracle and the HIP path can
+both consume exactly the same bits without sharing any of the method's code.
+
+Every generator uses ``numpy.random.default_rng(seed)`` (PCG64) and draws in
+the order written in its docstring.  Inputs meant for the FP32 path are rounded
+to float32 here and handed to both sides as the same values (the oracle reads
+them as float64).
+
+Media are plain dicts::
+
+    {"kind": "luneburg" | "gaussian" | "linear" | "homogeneous" | "fiber" | "grid",
+     "params": float64 array (layout per kind, see ``MEDIUM_PARAM_LAYOUT``),
+     "boundary": {"kind": "box" | "sphere" | "cylinder", "params": float64 array},
+     "n_amb": float,
+     # grid media only:
+     "grid": float32 array of shape (nz, ny, nx), x fastest,
+     "grid_lo": (3,) float64, "grid_hi": (3,) float64}
+
+Rays are ``(P0, d0)``: two (n, 3) float64 arrays (launch point, launch
+direction).  Trace settings are a dict ``{"dL0", "max_steps", "eps_tan",
+"crit_rad", "exit_plane_z"}``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Parameter layouts (documentation of the data format shared by both sides).
+MEDIUM_PARAM_LAYOUT = {
+    "homogeneous": "[n_h]",
+    "linear": "[n0, gx, gy, gz]            n = n0 + g.P",
+    "luneburg": "[R, cx, cy, cz]             n = sqrt(2 - |P-C|^2/R^2)",
+    "fiber": "[n_c, Delta, R, cx, cy]       parabolic core about the z axis through (cx, cy)",
+    "gaussian": "[n0, K, (A, sigma, cx, cy, cz) x K]",
+    "grid": "[] (values in 'grid', nodes spanning grid_lo..grid_hi)",
+}
+BOUNDARY_PARAM_LAYOUT = {
+    "box": "[lox, loy, loz, hix, hiy, hiz]",
+    "sphere": "[cx, cy, cz, r]",
+    "cylinder": "[cx, cy, r, z0, z1]   axis along z",
+}
+
+DEFAULT_CRIT_RAD = 1e-6
+
+
+def trace_params(dL0, max_steps, eps_tan=0.0, crit_rad=DEFAULT_CRIT_RAD, exit_plane_z=None):
+    return {"dL0": float(dL0), "max_steps": int(max_steps), "eps_tan": float(eps_tan),
+            "crit_rad": float(crit_rad),
+            "exit_plane_z": None if exit_plane_z is None else float(exit_plane_z)}
+
+
+def _f32(a):
+    """Round to float32 and return float64 holding exactly those values."""
+    return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def unit_box(n_amb=1.0):
+    return {"kind": "box", "params": np.array([0, 0, 0, 1, 1, 1], dtype=np.float64)}
+
+
+# ---------------------------------------------------------------------------
+# Luneburg sphere, parallel beam (accuracy configuration, FP64)
+# ---------------------------------------------------------------------------
+def luneburg_beam(n_side=64, R=1.0, z0=-1.5, dL0=1e-3, max_steps=20000):
+    """Luneburg sphere of radius R centred at the origin, n_amb = 1, beam along +z.
+
+    Launch grid: cell-centred ``x, y = -R + (k + 1/2) * 2R/n_side`` on the plane
+    z = z0; every ray has direction (0, 0, 1).  No random draws.
+    """
+    k = (np.arange(n_side, dtype=np.float64) + 0.5) * (2.0 * R / n_side) - R
+    X, Y = np.meshgrid(k, k, indexing="xy")
+    n = n_side * n_side
+    P0 = np.stack([X.ravel(), Y.ravel(), np.full(n, z0)], axis=1)
+    d0 = np.zeros((n, 3))
+    d0[:, 2] = 1.0
+    medium = {"kind": "luneburg", "params": np.array([R, 0.0, 0.0, 0.0]),
+              "boundary": {"kind": "sphere", "params": np.array([0.0, 0.0, 0.0, R])},
+              "n_amb": 1.0}
+    return medium, (P0, d0), trace_params(dL0, max_steps)
+
+
+# ---------------------------------------------------------------------------
+# Launch states on the z = 0 face of the unit cube
+# ---------------------------------------------------------------------------
+def face_cone_rays(n_rays, seed, cone_deg):
+    """Rays launched on the face z = 0 of the unit cube into a cone about +z.
+
+    Draw order (one generator): kx[n], ky[n] integers in [0, 2^23); cos(theta)
+    ~ U[cos(cone), 1) [n]; phi ~ U[0, 2pi) [n].  Positions are
+    x = (2k+1)/2^24, exactly representable in float32 and strictly inside
+    (0, 1), so no ray starts on a cube edge.  Directions are uniform in solid
+    angle inside the cone (in the ambient medium) and rounded to float32.
+    """
+    rng = np.random.default_rng(seed)
+    kx = rng.integers(0, 1 << 23, n_rays)
+    ky = rng.integers(0, 1 << 23, n_rays)
+    ct = rng.uniform(math.cos(math.radians(cone_deg)), 1.0, n_rays)
+    ph = rng.uniform(0.0, 2.0 * math.pi, n_rays)
+    P0 = np.zeros((n_rays, 3))
+    P0[:, 0] = (2.0 * kx + 1.0) / float(1 << 24)
+    P0[:, 1] = (2.0 * ky + 1.0) / float(1 << 24)
+    st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+    d0 = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=1)
+    return _f32(P0), _f32(d0)
+
+
+# ---------------------------------------------------------------------------
+# Freeform analytic medium: unit cube, 1.5 + sum of Gaussian bumps
+# ---------------------------------------------------------------------------
+def gaussian_medium(seed=2, K=16, n0=1.5, amp=0.1, wmin=0.05, wmax=0.3, n_amb=1.0):
+    """n = n0 + sum_k A_k exp(-|P - c_k|^2 / (2 sigma_k^2)) in the unit cube.
+
+    Draw order: A ~ U(-amp, amp) [K]; sigma ~ U(wmin, wmax) [K]; c ~ U(0,1) [K x 3].
+    All parameters rounded to float32.
+    """
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(-amp, amp, K)
+    s = rng.uniform(wmin, wmax, K)
+    c = rng.uniform(0.0, 1.0, (K, 3))
+    p = [n0, float(K)]
+    for k in range(K):
+        p += [A[k], s[k], c[k, 0], c[k, 1], c[k, 2]]
+    return {"kind": "gaussian", "params": _f32(np.array(p)),
+            "boundary": unit_box(), "n_amb": float(n_amb)}
+
+
+def gaussian_cube(n_rays=1 << 20, seed_medium=2, seed_rays=102, cone_deg=20.0,
+                  dL0=5e-4, max_steps=60000):
+    """Freeform analytic configuration: 16 seeded Gaussian bumps, 1M rays, 20 deg cone."""
+    medium = gaussian_medium(seed_medium)
+    rays = face_cone_rays(n_rays, seed_rays, cone_deg)
+    return medium, rays, trace_params(dL0, max_steps)
+
+
+# ---------------------------------------------------------------------------
+# Discretized isoindicial medium: quantized smoothed-noise grid
+# ---------------------------------------------------------------------------
+def noise_grid(N=256, seed=3, sigma_vox=8.0, nmin=1.4, nmax=1.8, levels=32):
+    """N^3 float32 index grid from periodic Gaussian-smoothed white noise.
+
+    Draw order: w ~ N(0,1) [N, N, N] (axis order z, y, x).  Smoothing is exact
+    periodic Gaussian filtering (multiplication of the FFT by
+    exp(-2 pi^2 sigma^2 f^2), f in cycles per voxel).  The result is mapped
+    affinely onto [nmin, nmax] and quantized to ``levels`` equally spaced values
+    n = nmin + q (nmax - nmin)/(levels - 1), q = round(...).
+    """
+    import scipy.fft as sfft
+
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((N, N, N))
+    W = sfft.rfftn(w, workers=-1)
+    del w
+    f = np.fft.fftfreq(N)
+    fr = np.fft.rfftfreq(N)
+    T = np.exp(-2.0 * math.pi ** 2 * sigma_vox ** 2 *
+               (f[:, None, None] ** 2 + f[None, :, None] ** 2 + fr[None, None, :] ** 2))
+    W *= T
+    v = sfft.irfftn(W, s=(N, N, N), workers=-1)
+    del W
+    lo, hi = v.min(), v.max()
+    v = (v - lo) / (hi - lo)
+    q = np.rint(v * (levels - 1))
+    n = nmin + q * ((nmax - nmin) / (levels - 1))
+    return n.astype(np.float32)
+
+
+def grid_medium(values, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), n_amb=1.0):
+    values = np.ascontiguousarray(values, dtype=np.float32)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    return {"kind": "grid", "params": np.zeros(0), "grid": values,
+            "grid_lo": lo, "grid_hi": hi,
+            "boundary": {"kind": "box", "params": np.concatenate([lo, hi])},
+            "n_amb": float(n_amb)}
+
+
+def quantized_grid_cube(n_rays=1 << 22, N=256, seed_grid=3, seed_rays=103,
+                        cone_deg=30.0, dL0=5e-4, max_steps=60000):
+    """Discretized configuration: 256^3 quantized grid, 4M rays, 30 deg cone."""
+    medium = grid_medium(noise_grid(N, seed_grid))
+    rays = face_cone_rays(n_rays, seed_rays, cone_deg)
+    return medium, rays, trace_params(dL0, max_steps)
+
+
+# ---------------------------------------------------------------------------
+# Differentiable design configuration (index-grid parameters + target ring)
+# ---------------------------------------------------------------------------
+def design_problem(N=64, n_side=512, seed_grid=4, seed_target=204, n0=1.5, jitter=0.01,
+                   ring_r=0.2, plane_z=1.2, dL0=5e-4, max_steps=60000):
+    """N^3 grid 1.5 + 0.01 N(0,1) (seed 4), n_side^2 parallel rays along +z from
+    cell centres of z = 0, exit plane z = plane_z, target points on a ring.
+
+    Draw orders: grid w ~ N(0,1) [N,N,N]; target phi ~ U[0, 2pi) [n_side^2].
+    """
+    rng = np.random.default_rng(seed_grid)
+    g = (n0 + jitter * rng.standard_normal((N, N, N))).astype(np.float32)
+    medium = grid_medium(g)
+    k = (np.arange(n_side, dtype=np.float64) + 0.5) / n_side
+    X, Y = np.meshgrid(k, k, indexing="xy")
+    n = n_side * n_side
+    P0 = _f32(np.stack([X.ravel(), Y.ravel(), np.zeros(n)], axis=1))
+    d0 = np.zeros((n, 3))
+    d0[:, 2] = 1.0
+    rt = np.random.default_rng(seed_target)
+    phi = rt.uniform(0.0, 2.0 * math.pi, n)
+    target = np.stack([0.5 + ring_r * np.cos(phi), 0.5 + ring_r * np.sin(phi)], axis=1)
+    return medium, (P0, d0), trace_params(dL0, max_steps, exit_plane_z=plane_z), target
+
+
+# ---------------------------------------------------------------------------
+# Served mix: a Poisson stream of trace jobs against resident media
+# ---------------------------------------------------------------------------
+def served_media(grid_sizes=(128, 160, 192, 256)):
+    """Eight media: four Gaussian-bump cubes (seeds 500..503) and four quantized
+    grids (seeds 504..507) with the given edge sizes."""
+    media = [gaussian_medium(500 + i) for i in range(4)]
+    for i, N in enumerate(grid_sizes):
+        media.append(grid_medium(noise_grid(N, 504 + i)))
+    return media
+
+
+def served_jobs(n_jobs=10000, seed_arrival=5, seed_sizes=105, rate_hz=100.0,
+                min_rays=1000, max_rays=4_000_000, n_media=8):
+    """Job stream: Poisson arrivals (exponential gaps, seed 5), ray counts
+    log-uniform in [min_rays, max_rays] (seed 105, draw order: log-size [n],
+    medium id [n], ray seed [n])."""
+    ra = np.random.default_rng(seed_arrival)
+    gaps = ra.exponential(1.0 / rate_hz, n_jobs)
+    t = np.cumsum(gaps)
+    rs = np.random.default_rng(seed_sizes)
+    size = np.exp(rs.uniform(math.log(min_rays), math.log(max_rays), n_jobs)).astype(np.int64)
+    med = rs.integers(0, n_media, n_jobs)
+    rseed = rs.integers(0, 2 ** 31 - 1, n_jobs)
+    return [{"t_arrival": float(t[j]), "n_rays": int(size[j]), "medium": int(med[j]),
+             "ray_seed": int(rseed[j])} for j in range(n_jobs)]
