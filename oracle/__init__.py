@@ -26,7 +26,7 @@ KINDS = {"homogeneous": 0, "linear": 1, "luneburg": 2, "fiber": 3, "gaussian": 4
 BOUNDARIES = {"box": 0, "sphere": 1, "cylinder": 2}
 
 EXITED, MISSED, TRUNCATED, NO_PLANE, INVALID_INPUT, REFLECTED_AT_ENTRY = range(6)
-F_NEAR_CRITICAL, F_TANGENT, F_STRAIGHT, F_BOUNDARY_TIR = 1, 2, 4, 8
+F_NEAR_CRITICAL, F_TANGENT, F_STRAIGHT, F_BOUNDARY_TIR, F_NEAR_TIE, F_NEAR_GRAZING = 1, 2, 4, 8, 16, 32
 
 
 def build(force=True):
@@ -52,7 +52,8 @@ class _Medium(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("dL0", C.c_double), ("max_steps", C.c_int64), ("eps_tan", C.c_double),
-                ("crit_rad", C.c_double), ("plane_z", C.c_double), ("has_plane", C.c_int32),
+                ("crit_rad", C.c_double), ("tie_eps", C.c_double), ("plane_z", C.c_double),
+                ("has_plane", C.c_int32),
                 ("pad", C.c_int32)]
 
 
@@ -113,6 +114,7 @@ def _params(p):
     q.max_steps = p["max_steps"]
     q.eps_tan = p.get("eps_tan", 0.0)
     q.crit_rad = p.get("crit_rad", 1e-6)
+    q.tie_eps = p.get("tie_eps", 1e-7)
     z = p.get("exit_plane_z")
     q.has_plane = 0 if z is None else 1
     q.plane_z = 0.0 if z is None else float(z)

@@ -32,7 +32,12 @@
  *     transmits the ray (EXITED) or reflects it (boundary TIR: the ray stays
  *     inside and moves on from P_B with dL0 / n(P_{i-1}));
  *   - every decision with mu > 1 is checked against the critical angle and
- *     flagged when |acos|N.I| - asin(1/mu)| < crit_rad.
+ *     flagged when |acos|N.I| - asin(1/mu)| < crit_rad; a refraction with
+ *     mu < 1 at |N.I| < crit_rad is flagged as near grazing (the sgn(N.I) of
+ *     Eq. (10) puts the refracted ray on one side of the isoindicial surface
+ *     or the other); a move whose end lies within tie_eps of the enclosing
+ *     surface, measured perpendicular to it, is flagged as a near tie (the
+ *     choice "full step or cut at the surface" is then decided by rounding).
  * The incident direction I_i is carried as the previous R (Eq. (6) gives the
  * same vector in exact arithmetic).
  */
@@ -555,6 +560,7 @@ interior_step:
                 double mu = n_last / ni; /* mu_i = n_{i-1} / n_i */
                 double D = 1.0 - mu * mu * (1.0 - c * c);
                 if (near_critical(mu, c, D, q->crit_rad)) o->flags |= ORC_F_NEAR_CRITICAL;
+                if (mu < 1.0 && fabs(c) < q->crit_rad) o->flags |= ORC_F_NEAR_GRAZING;
                 if (D <= 0.0) {
                     /* case (v): TIR, Eqs. (19)-(20) */
                     reflect(I, N, c, R);
@@ -571,6 +577,13 @@ interior_step:
         for (;;) {
             double tx = exit_dist(m, P, R, &face);
             o->steps++;
+            if (tx < 3.0 * Delta) {
+                /* distance of the step end from the surface, perpendicular to it */
+                double Pe[3], Ne[3];
+                for (int a = 0; a < 3; ++a) Pe[a] = P[a] + tx * R[a];
+                outward_normal(m, Pe, face, Ne);
+                if (fabs(tx - Delta) * fabs(dot3(R, Ne)) < q->tie_eps) o->flags |= ORC_F_NEAR_TIE;
+            }
             if (tx > Delta) {
                 /* Eq. (3) */
                 for (int a = 0; a < 3; ++a) P[a] = P[a] + Delta * R[a];

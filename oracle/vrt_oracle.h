@@ -41,7 +41,9 @@ enum {
 
 /* per-ray flag bits */
 enum {
-    ORC_F_NEAR_CRITICAL = 1, ORC_F_TANGENT = 2, ORC_F_STRAIGHT = 4, ORC_F_BOUNDARY_TIR = 8
+    ORC_F_NEAR_CRITICAL = 1, ORC_F_TANGENT = 2, ORC_F_STRAIGHT = 4, ORC_F_BOUNDARY_TIR = 8,
+    ORC_F_NEAR_TIE = 16,    /* a step ended within tie_eps (perpendicular) of the surface */
+    ORC_F_NEAR_GRAZING = 32 /* a refraction into higher index had |N.I| < crit_rad */
 };
 
 typedef struct {
@@ -61,6 +63,7 @@ typedef struct {
     int64_t max_steps;   /* guard for trapped rays -> ORC_TRUNCATED */
     double eps_tan;      /* |N.I| <= eps_tan selects the tangential rule (iv) */
     double crit_rad;     /* near-critical flag window in radians */
+    double tie_eps;      /* near-tie flag window: distance of a step end from the surface */
     double plane_z;      /* exit plane z (used when has_plane != 0) */
     int32_t has_plane;
     int32_t pad;

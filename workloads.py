@@ -22,7 +22,7 @@ Media are plain dicts::
 
 Rays are ``(P0, d0)``: two (n, 3) float64 arrays (launch point, launch
 direction).  Trace settings are a dict ``{"dL0", "max_steps", "eps_tan",
-"crit_rad", "exit_plane_z"}``.
+"crit_rad", "tie_eps", "exit_plane_z"}``.
 """
 from __future__ import annotations
 
@@ -46,11 +46,13 @@ BOUNDARY_PARAM_LAYOUT = {
 }
 
 DEFAULT_CRIT_RAD = 1e-6
+DEFAULT_TIE_EPS = 1e-7
 
 
-def trace_params(dL0, max_steps, eps_tan=0.0, crit_rad=DEFAULT_CRIT_RAD, exit_plane_z=None):
+def trace_params(dL0, max_steps, eps_tan=0.0, crit_rad=DEFAULT_CRIT_RAD, exit_plane_z=None,
+                 tie_eps=DEFAULT_TIE_EPS):
     return {"dL0": float(dL0), "max_steps": int(max_steps), "eps_tan": float(eps_tan),
-            "crit_rad": float(crit_rad),
+            "crit_rad": float(crit_rad), "tie_eps": float(tie_eps),
             "exit_plane_z": None if exit_plane_z is None else float(exit_plane_z)}
 
 
@@ -90,17 +92,20 @@ def luneburg_beam(n_side=64, R=1.0, z0=-1.5, dL0=1e-3, max_steps=20000):
 def face_cone_rays(n_rays, seed, cone_deg):
     """Rays launched on the face z = 0 of the unit cube into a cone about +z.
 
-    Draw order (one generator): kx[n], ky[n] integers in [0, 2^23); cos(theta)
-    ~ U[cos(cone), 1) [n]; phi ~ U[0, 2pi) [n].  Positions are
-    x = (2k+1)/2^24, exactly representable in float32 and strictly inside
-    (0, 1), so no ray starts on a cube edge.  Directions are uniform in solid
-    angle inside the cone (in the ambient medium) and rounded to float32.
+    One draw u ~ U[0,1) of shape (n_rays, 4); row i belongs to ray i, so the
+    first m rays are the same for every n_rays >= m.  Per ray:
+    kx = floor(u0 2^23), ky = floor(u1 2^23), cos(theta) = 1 - u2 (1 - cos(cone)),
+    phi = 2 pi u3.  Positions are x = (2k+1)/2^24, exactly representable in
+    float32 and strictly inside (0, 1), so no ray starts on a cube edge.
+    Directions are uniform in solid angle inside the cone (in the ambient
+    medium) and rounded to float32.
     """
     rng = np.random.default_rng(seed)
-    kx = rng.integers(0, 1 << 23, n_rays)
-    ky = rng.integers(0, 1 << 23, n_rays)
-    ct = rng.uniform(math.cos(math.radians(cone_deg)), 1.0, n_rays)
-    ph = rng.uniform(0.0, 2.0 * math.pi, n_rays)
+    u = rng.random((n_rays, 4))
+    kx = np.floor(u[:, 0] * (1 << 23))
+    ky = np.floor(u[:, 1] * (1 << 23))
+    ct = 1.0 - u[:, 2] * (1.0 - math.cos(math.radians(cone_deg)))
+    ph = 2.0 * math.pi * u[:, 3]
     P0 = np.zeros((n_rays, 3))
     P0[:, 0] = (2.0 * kx + 1.0) / float(1 << 24)
     P0[:, 1] = (2.0 * ky + 1.0) / float(1 << 24)
