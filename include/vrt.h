@@ -1,0 +1,204 @@
+/*
+ * vrt.h -- C ABI of libvrt, the MI355X (gfx950) library for the constant
+ * optical-path-length vectorial ray march (VRT) through gradient-index media.
+ *
+ * The method (Sec. II of "Generalized vectorial ray tracing for optical
+ * analysis and design in freeform gradient-index media"): a ray advances in
+ * steps of constant optical path length dL0, i.e. geometric length
+ * Delta_i = dL0 / n_i (Eqs. (3)-(4)).  At every point P_i the library
+ * evaluates n and grad n, takes the local isoindicial normal N = grad n/|grad n|
+ * (Eq. (5)) and applies the vectorial law of refraction R = mu I + gamma N
+ * (Eqs. (9)-(10), mu = n(P_{i-1}) / n(P_i)), total internal reflection when
+ * mu^2 (1 - (N.I)^2) >= 1 (Eqs. (19)-(20), the reflected step uses
+ * Delta_{i-1}), the tangential arc rule when N.I = 0 (Eqs. (16)-(18)) and a
+ * straight step where the gradient vanishes or is undefined (Eqs. (11)-(12)).
+ * Where the step would cross the enclosing surface it is cut there and the
+ * same law is applied with the surface normal (case (i)): the ray leaves into
+ * the homogeneous surroundings or is reflected back inside.
+ *
+ * Conventions
+ *   - Every function returns VRT_OK (0) or a negative vrt_error; nothing
+ *     throws across the ABI.  vrt_last_error() gives a thread-local message
+ *     for the most recent failure on the calling thread.
+ *   - "device pointer" means memory on the context's HIP device (e.g. the
+ *     data_ptr() of a torch tensor on that device).  The caller owns every ray
+ *     and result buffer; the library never frees them.
+ *   - The library owns the device copies of media until vrt_medium_destroy.
+ *   - vrt_trace is asynchronous on the given HIP stream (a hipStream_t passed
+ *     as void*; NULL = the null stream).  Results are valid once the stream
+ *     has been synchronised.  Calls on one medium from several streams may
+ *     overlap; the library keeps no per-trace mutable state on the medium
+ *     except its ray-queue counter, which is per call (see vrt_trace).
+ */
+#ifndef VRT_H
+#define VRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VRT_ABI_VERSION 1
+
+typedef struct vrt_context_s *vrt_context_t;
+typedef struct vrt_medium_s *vrt_medium_t;
+
+/* return codes */
+enum vrt_error {
+    VRT_OK = 0,
+    VRT_EINVAL = -1,       /* bad argument: null/misaligned pointer, dL0 <= 0, n <= 0, NaN parameter */
+    VRT_ENOMEM = -2,       /* device allocation failed */
+    VRT_EHIP = -3,         /* HIP runtime error; the message carries hipGetErrorString */
+    VRT_EUNSUPPORTED = -4  /* valid request this build does not implement */
+};
+
+/* medium kinds (index distributions n(P)) */
+enum vrt_medium_kind {
+    VRT_MEDIUM_HOMOGENEOUS = 0, /* params [n_h]                        Sec. II case (iii)          */
+    VRT_MEDIUM_LINEAR = 1,      /* params [n0, gx, gy, gz]             n = n0 + g.P (stratified)   */
+    VRT_MEDIUM_LUNEBURG = 2,    /* params [R, cx, cy, cz]              n = sqrt(2 - |P-C|^2/R^2)  */
+    VRT_MEDIUM_FIBER = 3,       /* params [n_c, Delta, R, cx, cy]      Sec. IV, Eq. (21), axis z   */
+    VRT_MEDIUM_GAUSSIAN = 4,    /* params [n0, K, (A, sigma, cx, cy, cz) x K], K <= VRT_MAX_BUMPS
+                                   n = n0 + sum A exp(-|P-c|^2 / (2 sigma^2))                     */
+    VRT_MEDIUM_GRID = 5         /* discretized medium, see vrt_medium_create_grid                  */
+};
+#define VRT_MAX_BUMPS 64
+
+/* enclosing convex surface (Sec. II case (i)) */
+enum vrt_boundary_kind {
+    VRT_BOUNDARY_BOX = 0,      /* params [lox, loy, loz, hix, hiy, hiz]   */
+    VRT_BOUNDARY_SPHERE = 1,   /* params [cx, cy, cz, r]                  */
+    VRT_BOUNDARY_CYLINDER = 2  /* params [cx, cy, r, z0, z1], axis along z */
+};
+
+typedef struct {
+    int32_t kind;     /* vrt_boundary_kind */
+    int32_t reserved; /* must be 0 */
+    double params[6];
+} vrt_boundary;
+
+/* arithmetic of the march */
+enum vrt_precision {
+    VRT_FP64 = 0,      /* plain double-precision march, one lane per ray, one launch per batch */
+    VRT_FP32_COMP = 1  /* single precision with compensated position / direction accumulation,
+                          double precision for the refraction/TIR discriminant, surface events
+                          and the exit plane; persistent lanes refilled from a ray queue */
+};
+
+typedef struct {
+    double dL0;           /* optical path length per step (> 0), Eqs. (3)-(4) */
+    int64_t max_steps;    /* per-ray step budget (> 0); rays that use it up end TRUNCATED */
+    double eps_tan;       /* |N.I| <= eps_tan selects the tangential rule (iv); 0 = exact zero only */
+    double crit_rad;      /* near-critical flag window (radians, >= 0) */
+    double tie_eps;       /* near-tie flag window (length, >= 0, <= 1e-6), see VRT_FLAG_NEAR_TIE */
+    double exit_plane_z;  /* NaN: no exit plane; otherwise exiting rays are continued
+                             straight to z = exit_plane_z (status NO_PLANE if they cannot) */
+    int32_t precision;    /* vrt_precision */
+    int32_t reserved;     /* must be 0 */
+} vrt_trace_params;
+
+/* Ray batch, structure of arrays, all device pointers.  Element type is
+ * double for VRT_FP64 and float for VRT_FP32_COMP.  Inputs: launch point
+ * (px,py,pz) and launch direction (dx,dy,dz, any non-zero length; it is
+ * normalised).  Outputs: exit point (ox,oy,oz) -- on the surface, or on the
+ * exit plane when one is set -- and exit direction (odx,ody,odz); per-ray
+ * status (vrt_ray_status), steps (moves made, including moves cut at the
+ * surface), n_tir (interior TIRs), n_btir (TIRs at the surface) and flags
+ * (vrt_ray_flag bits).  Input and output arrays must not overlap. */
+typedef struct {
+    const void *px, *py, *pz, *dx, *dy, *dz;
+    void *ox, *oy, *oz, *odx, *ody, *odz;
+    uint32_t *status, *steps, *n_tir, *n_btir, *flags;
+} vrt_rays;
+
+enum vrt_ray_status {
+    VRT_RAY_EXITED = 0,
+    VRT_RAY_MISSED = 1,             /* launched outside, the line misses the medium */
+    VRT_RAY_TRUNCATED = 2,          /* max_steps used up; exit state = last point / direction */
+    VRT_RAY_NO_PLANE = 3,           /* exited, but cannot reach the exit plane; exit state on the surface */
+    VRT_RAY_INVALID_INPUT = 4,      /* non-finite launch state or zero direction */
+    VRT_RAY_REFLECTED_AT_ENTRY = 5  /* TIR at the entry point (denser surroundings) */
+};
+
+enum vrt_ray_flag {
+    VRT_FLAG_NEAR_CRITICAL = 1, /* some decision with mu > 1 had |acos|N.I| - asin(1/mu)| < crit_rad */
+    VRT_FLAG_TANGENT = 2,       /* the tangential rule (iv) was used */
+    VRT_FLAG_STRAIGHT = 4,      /* a straight step at zero / undefined gradient (ii)/(iii) */
+    VRT_FLAG_BOUNDARY_TIR = 8,  /* reflected at the enclosing surface at least once */
+    VRT_FLAG_NEAR_TIE = 16,     /* some move ended within tie_eps of the enclosing surface,
+                                   measured perpendicular to it ("full step or cut" is then
+                                   decided by rounding) */
+    VRT_FLAG_NEAR_GRAZING = 32  /* some refraction with mu < 1 had |N.I| < crit_rad (Eq. (10)
+                                   sends the ray to the side of the isoindicial surface given
+                                   by sgn(N.I)) */
+};
+
+typedef struct {
+    uint64_t rays, steps, exited, missed, truncated, no_plane, invalid, reflected_at_entry;
+    uint64_t tir_interior, tir_boundary, flagged_near_critical, tangent, straight, flagged_near_tie;
+    uint64_t flagged_near_grazing;
+} vrt_counters;
+
+/* Version of this ABI (VRT_ABI_VERSION). */
+int vrt_abi_version(void);
+
+/* Create a context on HIP device `hip_device` (makes it current for the
+ * calling thread).  *out receives the handle.  Errors: EINVAL (bad device or
+ * null out), EHIP. */
+int vrt_context_create(int hip_device, vrt_context_t *out);
+
+/* Destroy a context.  All media created on it must have been destroyed.
+ * Errors: EINVAL (null, or media still alive). */
+int vrt_context_destroy(vrt_context_t ctx);
+
+/* Create an analytic medium (kind != GRID) inside boundary `bnd`, surrounded
+ * by a homogeneous medium of index n_ambient.  params: host array of
+ * n_params doubles (layout in vrt_medium_kind); copied, the caller keeps
+ * ownership.  Errors: EINVAL (unknown kind, wrong n_params, n <= 0 or
+ * non-finite parameters, K > VRT_MAX_BUMPS), ENOMEM, EHIP. */
+int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params, int n_params,
+                               const vrt_boundary *bnd, double n_ambient, vrt_medium_t *out);
+
+/* Create a discretized medium from nx*ny*nz float index values (x fastest,
+ * then y, then z) at nodes x_i = lo + i (hi - lo)/(nx - 1) (same for y, z),
+ * bounded by the box [lo, hi] in surroundings of index n_ambient.  Between
+ * nodes n is the trilinear interpolant and grad n the trilinear interpolant
+ * of the node central differences (one-sided at the first and last node).
+ * `values` is a host pointer if values_on_device == 0, else a device pointer;
+ * it is copied either way.  Each dimension must be >= 2 and <= 4096.
+ * Errors: EINVAL (sizes, non-positive or non-finite values, lo >= hi),
+ * ENOMEM, EHIP. */
+int vrt_medium_create_grid(vrt_context_t ctx, const float *values, int nx, int ny, int nz,
+                           const double lo[3], const double hi[3], double n_ambient,
+                           int values_on_device, vrt_medium_t *out);
+
+/* Destroy a medium.  Waits for the device to finish work issued on it
+ * (device-wide synchronisation) before freeing.  Errors: EINVAL. */
+int vrt_medium_destroy(vrt_medium_t m);
+
+/* Device memory held by the medium, in bytes. */
+int vrt_medium_device_bytes(vrt_medium_t m, size_t *out);
+
+/* Trace n_rays rays (asynchronous on `stream`).  n_rays may be 0 (no-op).
+ * Errors (nothing is launched): EINVAL for null/misaligned pointers, dL0 <= 0,
+ * max_steps <= 0, reserved != 0, unknown precision, n_rays >= 2^32;
+ * EUNSUPPORTED for combinations this build does not implement; EHIP for
+ * launch failures. */
+int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, size_t n_rays,
+              void *stream);
+
+/* Sum the per-ray outputs of a finished trace (status, steps, n_tir, n_btir,
+ * flags of `rays`) into *out.  Runs a reduction kernel on `stream` and
+ * synchronises that stream.  Errors: EINVAL, EHIP. */
+int vrt_reduce_counters(vrt_context_t ctx, const vrt_rays *rays, size_t n_rays,
+                        vrt_counters *out, void *stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *vrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VRT_H */

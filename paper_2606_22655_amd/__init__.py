@@ -1,0 +1,299 @@
+"""Python binding of libvrt (include/vrt.h): the constant-OPL vectorial ray
+march through gradient-index media on MI355X (gfx950).
+
+The functions named ``vrt_*`` mirror the C entry points one to one and only
+marshal arguments; every step of the march runs in the HIP kernels of
+``libvrt.so``.  PyTorch provides device memory and the HIP stream.  There is
+no CPU fallback: if the library has not been built, or no GPU is present,
+the calls raise.
+
+Convenience layer: ``Context``, ``Medium`` (built from the medium dicts of
+``workloads.py``) and ``trace`` (torch tensors in, dict of tensors out).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvrt.so")
+
+VRT_OK, VRT_EINVAL, VRT_ENOMEM, VRT_EHIP, VRT_EUNSUPPORTED = 0, -1, -2, -3, -4
+MEDIUM_KINDS = {"homogeneous": 0, "linear": 1, "luneburg": 2, "fiber": 3, "gaussian": 4, "grid": 5}
+BOUNDARY_KINDS = {"box": 0, "sphere": 1, "cylinder": 2}
+VRT_FP64, VRT_FP32_COMP = 0, 1
+PRECISIONS = {"fp64": VRT_FP64, "fp32c": VRT_FP32_COMP}
+STATUS = {"EXITED": 0, "MISSED": 1, "TRUNCATED": 2, "NO_PLANE": 3, "INVALID_INPUT": 4,
+          "REFLECTED_AT_ENTRY": 5}
+FLAG_NEAR_CRITICAL, FLAG_TANGENT, FLAG_STRAIGHT, FLAG_BOUNDARY_TIR, FLAG_NEAR_TIE = 1, 2, 4, 8, 16
+FLAG_NEAR_GRAZING = 32
+
+EXPORTED = ["vrt_abi_version", "vrt_context_create", "vrt_context_destroy",
+            "vrt_medium_create_analytic", "vrt_medium_create_grid", "vrt_medium_destroy",
+            "vrt_medium_device_bytes", "vrt_trace", "vrt_reduce_counters", "vrt_last_error"]
+
+
+class VrtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libvrt error {code}: {msg}")
+        self.code = code
+
+
+class vrt_boundary(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("params", C.c_double * 6)]
+
+
+class vrt_trace_params(C.Structure):
+    _fields_ = [("dL0", C.c_double), ("max_steps", C.c_int64), ("eps_tan", C.c_double),
+                ("crit_rad", C.c_double), ("tie_eps", C.c_double), ("exit_plane_z", C.c_double),
+                ("precision", C.c_int32), ("reserved", C.c_int32)]
+
+
+class vrt_rays(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("px", "py", "pz", "dx", "dy", "dz", "ox", "oy", "oz",
+                                          "odx", "ody", "odz", "status", "steps", "n_tir",
+                                          "n_btir", "flags")]
+
+
+COUNTER_FIELDS = ["rays", "steps", "exited", "missed", "truncated", "no_plane", "invalid",
+                  "reflected_at_entry", "tir_interior", "tir_boundary", "flagged_near_critical",
+                  "tangent", "straight", "flagged_near_tie", "flagged_near_grazing"]
+
+
+class vrt_counters(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in COUNTER_FIELDS]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libvrt.so and declare its entry points (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libvrt.so is not built ({path}); run "
+                          "`python -m paper_2606_22655_amd.build` first")
+    lib = C.CDLL(path)
+    vp, i32 = C.c_void_p, C.c_int
+    lib.vrt_abi_version.restype = i32
+    lib.vrt_abi_version.argtypes = []
+    lib.vrt_context_create.argtypes = [i32, C.POINTER(vp)]
+    lib.vrt_context_destroy.argtypes = [vp]
+    lib.vrt_medium_create_analytic.argtypes = [vp, i32, C.POINTER(C.c_double), i32,
+                                               C.POINTER(vrt_boundary), C.c_double, C.POINTER(vp)]
+    lib.vrt_medium_create_grid.argtypes = [vp, vp, i32, i32, i32, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_double), C.c_double, i32, C.POINTER(vp)]
+    lib.vrt_medium_destroy.argtypes = [vp]
+    lib.vrt_medium_device_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    lib.vrt_trace.argtypes = [vp, C.POINTER(vrt_trace_params), C.POINTER(vrt_rays), C.c_size_t, vp]
+    lib.vrt_reduce_counters.argtypes = [vp, C.POINTER(vrt_rays), C.c_size_t,
+                                        C.POINTER(vrt_counters), vp]
+    lib.vrt_last_error.restype = C.c_char_p
+    lib.vrt_last_error.argtypes = []
+    for name in EXPORTED:
+        if name not in ("vrt_last_error", "vrt_abi_version"):
+            getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != VRT_OK:
+        raise VrtError(rc, vrt_last_error())
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# one-to-one entry points
+# ---------------------------------------------------------------------------
+def vrt_abi_version():
+    return load_library().vrt_abi_version()
+
+
+def vrt_last_error():
+    return (load_library().vrt_last_error() or b"").decode()
+
+
+def vrt_context_create(device=0):
+    h = C.c_void_p()
+    _check(load_library().vrt_context_create(int(device), C.byref(h)))
+    return h
+
+
+def vrt_context_destroy(ctx):
+    _check(load_library().vrt_context_destroy(ctx))
+
+
+def vrt_medium_create_analytic(ctx, kind, params, boundary, n_ambient):
+    arr = (C.c_double * len(params))(*[float(x) for x in params])
+    h = C.c_void_p()
+    _check(load_library().vrt_medium_create_analytic(ctx, int(kind), arr, len(params),
+                                                     C.byref(boundary), float(n_ambient),
+                                                     C.byref(h)))
+    return h
+
+
+def vrt_medium_create_grid(ctx, values_ptr, nx, ny, nz, lo, hi, n_ambient, values_on_device):
+    lo3 = (C.c_double * 3)(*[float(x) for x in lo])
+    hi3 = (C.c_double * 3)(*[float(x) for x in hi])
+    h = C.c_void_p()
+    _check(load_library().vrt_medium_create_grid(ctx, C.c_void_p(values_ptr), int(nx), int(ny),
+                                                 int(nz), lo3, hi3, float(n_ambient),
+                                                 int(values_on_device), C.byref(h)))
+    return h
+
+
+def vrt_medium_destroy(m):
+    _check(load_library().vrt_medium_destroy(m))
+
+
+def vrt_medium_device_bytes(m):
+    v = C.c_size_t()
+    _check(load_library().vrt_medium_device_bytes(m, C.byref(v)))
+    return v.value
+
+
+def vrt_trace(medium, params, rays, n_rays, stream):
+    return _check(load_library().vrt_trace(medium, C.byref(params), C.byref(rays), int(n_rays),
+                                           C.c_void_p(stream)))
+
+
+def vrt_reduce_counters(ctx, rays, n_rays, stream):
+    out = vrt_counters()
+    _check(load_library().vrt_reduce_counters(ctx, C.byref(rays), int(n_rays), C.byref(out),
+                                              C.c_void_p(stream)))
+    return {k: int(getattr(out, k)) for k in COUNTER_FIELDS}
+
+
+# ---------------------------------------------------------------------------
+# convenience layer over torch tensors
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+
+    return torch
+
+
+class Context:
+    def __init__(self, device=0):
+        self.device = int(device)
+        self.handle = vrt_context_create(self.device)
+
+    def close(self):
+        if self.handle is not None:
+            vrt_context_destroy(self.handle)
+            self.handle = None
+
+
+class Medium:
+    """Device-resident medium built from a ``workloads`` medium dict."""
+
+    def __init__(self, ctx, spec):
+        self.ctx = ctx
+        self.spec = spec
+        kind = spec["kind"]
+        if kind == "grid":
+            torch = _torch()
+            g = spec["grid"]
+            t = torch.as_tensor(g, dtype=torch.float32).contiguous()
+            nz, ny, nx = t.shape
+            self.handle = vrt_medium_create_grid(ctx.handle, t.data_ptr(), nx, ny, nz,
+                                                 spec["grid_lo"], spec["grid_hi"], spec["n_amb"], 0)
+        else:
+            b = vrt_boundary()
+            b.kind = BOUNDARY_KINDS[spec["boundary"]["kind"]]
+            for i, v in enumerate(spec["boundary"]["params"]):
+                b.params[i] = float(v)
+            self.handle = vrt_medium_create_analytic(ctx.handle, MEDIUM_KINDS[kind],
+                                                     list(spec["params"]), b, spec["n_amb"])
+
+    @property
+    def device_bytes(self):
+        return vrt_medium_device_bytes(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            vrt_medium_destroy(self.handle)
+            self.handle = None
+
+
+def make_params(p, precision):
+    q = vrt_trace_params()
+    q.dL0 = float(p["dL0"])
+    q.max_steps = int(p["max_steps"])
+    q.eps_tan = float(p.get("eps_tan", 0.0))
+    q.crit_rad = float(p.get("crit_rad", 1e-6))
+    q.tie_eps = float(p.get("tie_eps", 1e-7))
+    z = p.get("exit_plane_z")
+    q.exit_plane_z = math.nan if z is None else float(z)
+    q.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    q.reserved = 0
+    return q
+
+
+class RayBatch:
+    """Structure-of-arrays device buffers for one trace."""
+
+    def __init__(self, P0, d0, precision, device="cuda"):
+        torch = _torch()
+        dt = torch.float64 if precision in ("fp64", VRT_FP64) else torch.float32
+        P0 = torch.as_tensor(P0, dtype=dt)
+        d0 = torch.as_tensor(d0, dtype=dt)
+        n = P0.shape[0]
+        self.n = n
+        self.inp = torch.empty((6, n), dtype=dt, device=device)
+        self.inp[0:3].copy_(P0.T)
+        self.inp[3:6].copy_(d0.T)
+        self.out = torch.empty((6, n), dtype=dt, device=device)
+        self.u32 = torch.empty((5, n), dtype=torch.int32, device=device)
+        self.rays = vrt_rays()
+        names_in = ("px", "py", "pz", "dx", "dy", "dz")
+        names_out = ("ox", "oy", "oz", "odx", "ody", "odz")
+        for i, k in enumerate(names_in):
+            setattr(self.rays, k, self.inp[i].data_ptr() if n else None)
+        for i, k in enumerate(names_out):
+            setattr(self.rays, k, self.out[i].data_ptr() if n else None)
+        for i, k in enumerate(("status", "steps", "n_tir", "n_btir", "flags")):
+            setattr(self.rays, k, self.u32[i].data_ptr() if n else None)
+
+    def results(self):
+        """Exit state as CPU numpy arrays (synchronises)."""
+        o = self.out.double().cpu().numpy()
+        u = self.u32.cpu().numpy().view("uint32")
+        return {"P": o[0:3].T.copy(), "D": o[3:6].T.copy(), "status": u[0].copy(),
+                "steps": u[1].copy(), "ntir": u[2].copy(), "nbtir": u[3].copy(),
+                "flags": u[4].copy()}
+
+
+def trace(medium, batch, params, precision, stream=None):
+    """Enqueue the march of ``batch`` through ``medium`` on ``stream``
+    (default: torch's current stream)."""
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    vrt_trace(medium.handle, make_params(params, precision), batch.rays, batch.n, stream)
+
+
+def counters(ctx, batch, stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    return vrt_reduce_counters(ctx.handle, batch.rays, batch.n, stream)
+
+
+def trace_numpy(spec, rays, params, precision="fp32c", device=0):
+    """One-shot helper: build the medium, trace (P0, d0), return numpy results."""
+    torch = _torch()
+    ctx = Context(device)
+    med = Medium(ctx, spec)
+    try:
+        b = RayBatch(rays[0], rays[1], precision)
+        trace(med, b, params, precision)
+        torch.cuda.synchronize()
+        return b.results()
+    finally:
+        med.close()
+        ctx.close()

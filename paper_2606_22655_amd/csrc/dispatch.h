@@ -1,0 +1,25 @@
+// dispatch.h -- launch arguments shared by the host API and the march kernels.
+#pragma once
+
+#include "media.h"
+
+namespace vrt {
+
+struct LaunchArgs {
+    MediumDev m;
+    MedF mf;
+    BoundaryDev b;
+    TraceDev t;
+    RaysDev<double> io64;
+    RaysDev<float> io32;
+    uint32_t n;
+    hipStream_t stream;
+    uint32_t *queue;  // FP32_COMP: ray-queue counter (device), zeroed by the launcher
+    int num_cu;
+    int blocks_per_cu;  // FP32_COMP persistent grid: blocks of 256 lanes per CU (0 = default)
+};
+
+hipError_t launch_march_fp64(const LaunchArgs &a);
+hipError_t launch_march_fp32c(const LaunchArgs &a);
+
+}  // namespace vrt

@@ -1,0 +1,234 @@
+// media.h -- index distributions n(P) and grad n(P) on the device.
+//
+// Two evaluators per medium:
+//   med64<K>  double precision n and grad n (plain march, surface events and
+//             the near-grazing decisions of the single-precision march).  Each
+//             formula is evaluated in the order it is written (n, then the
+//             gradient by the chain rule), with divisions kept as divisions,
+//             so that with FMA contraction disabled the results are the
+//             correctly rounded steps of the textbook expressions;
+//   med32<K>  single precision n and grad n at P_i plus the index difference
+//             dn = n(P_i) - n(P_{i-1}) along the last move s = P_i - P_{i-1},
+//             computed from s directly instead of as the difference of two
+//             rounded indices.  The vectorial law only needs mu_i - 1 =
+//             -dn / n_i (Eqs. (9)-(10), (19)); near isoindicial turning points
+//             dn is ~1e-8 while a rounded index carries ~1e-7 of error, so the
+//             difference form is what keeps the single-precision march on the
+//             same side of every refraction/TIR decision as a double one.
+//
+// Parameter storage (MediumDev.q, raw as given to vrt_medium_create_analytic):
+//   HOMOGENEOUS [n]  LINEAR [n0, gx, gy, gz]  LUNEBURG [R, cx, cy, cz]
+//   FIBER [n_c, Delta, R, cx, cy]  GAUSSIAN [n0] + bumps_d (A, sigma, cx, cy, cz) x K
+// MedF.q holds single-precision derived constants (see vrt_api.hip).
+// Discretized media keep the node values and node records
+// (n, h_x, h_y, h_z) where h_a is the central difference of the node values
+// along axis a divided by the number of node spacings it spans (2, or 1 at
+// the first/last node): exact in float for nearby values; grad n = h * inv_h.
+#pragma once
+
+#include "vrt_common.h"
+
+namespace vrt {
+
+// ---------------------------------------------------------------------------
+// double precision
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double grid_node64(const MediumDev &m, int i, int j, int k) {
+    return (double)m.grid[((size_t)k * m.ny + j) * m.nx + i];
+}
+
+// node central difference along axis a (one-sided at the first/last node)
+__device__ inline double grid_cdiff64(const MediumDev &m, int i, int j, int k, int a) {
+    const int nn = a == 0 ? m.nx : (a == 1 ? m.ny : m.nz);
+    const int idx = a == 0 ? i : (a == 1 ? j : k);
+    int lo = idx, hi = idx;
+    double span;
+    if (idx == 0) {
+        hi = 1;
+        span = m.h[a];
+    } else if (idx == nn - 1) {
+        lo = nn - 2;
+        span = m.h[a];
+    } else {
+        lo = idx - 1;
+        hi = idx + 1;
+        span = 2.0 * m.h[a];
+    }
+    const double vh = a == 0 ? grid_node64(m, hi, j, k)
+                             : (a == 1 ? grid_node64(m, i, hi, k) : grid_node64(m, i, j, hi));
+    const double vl = a == 0 ? grid_node64(m, lo, j, k)
+                             : (a == 1 ? grid_node64(m, i, lo, k) : grid_node64(m, i, j, lo));
+    return (vh - vl) / span;
+}
+
+__device__ inline void grid_cell64(const MediumDev &m, d3 P, int c[3], double f[3]) {
+    const int nn[3] = {m.nx, m.ny, m.nz};
+    for (int a = 0; a < 3; ++a) {
+        double x = get(P, a);
+        x = x < m.lo[a] ? m.lo[a] : (x > m.hi[a] ? m.hi[a] : x);
+        const double u = (x - m.lo[a]) / m.h[a];
+        int ci = (int)floor(u);
+        ci = ci < 0 ? 0 : (ci > nn[a] - 2 ? nn[a] - 2 : ci);
+        c[a] = ci;
+        f[a] = u - (double)ci;
+    }
+}
+
+template <int MK>
+__device__ inline void med64(const MediumDev &m, d3 P, double &n, d3 &g) {
+    const double *p = m.q;
+    if constexpr (MK == VRT_MEDIUM_HOMOGENEOUS) {
+        n = p[0];
+        g = mk(0, 0, 0);
+    } else if constexpr (MK == VRT_MEDIUM_LINEAR) {
+        n = p[0] + p[1] * P.x + p[2] * P.y + p[3] * P.z;
+        g = mk(p[1], p[2], p[3]);
+    } else if constexpr (MK == VRT_MEDIUM_LUNEBURG) {
+        // n = sqrt(2 - r^2/R^2), grad n = -(P - C) / (R^2 n)
+        const double R = p[0];
+        const d3 o = P - mk(p[1], p[2], p[3]);
+        n = sqrt(2.0 - dot(o, o) / (R * R));
+        g = mk(-o.x / (R * R * n), -o.y / (R * R * n), -o.z / (R * R * n));
+    } else if constexpr (MK == VRT_MEDIUM_FIBER) {
+        // Sec. IV, Eq. (21): core n^2 = n_c^2 (1 - 2 Delta rho^2 / R^2); cladding constant
+        const double nc = p[0], Dl = p[1], R = p[2];
+        const double x = P.x - p[3], y = P.y - p[4];
+        const double r2 = x * x + y * y;
+        if (r2 <= R * R) {
+            n = nc * sqrt(1.0 - 2.0 * Dl * r2 / (R * R));
+            const double k = -2.0 * Dl * nc * nc / (R * R * n);
+            g = mk(k * x, k * y, 0.0);
+        } else {
+            n = nc * sqrt(1.0 - 2.0 * Dl);
+            g = mk(0, 0, 0);
+        }
+    } else if constexpr (MK == VRT_MEDIUM_GAUSSIAN) {
+        // n = n0 + sum A exp(-|P - c|^2 / (2 sigma^2)), grad = -sum A e (P - c) / sigma^2
+        n = p[0];
+        g = mk(0, 0, 0);
+        for (int k = 0; k < m.K; ++k) {
+            const double *b = m.bumps_d + 5 * k;
+            const double A = b[0], s = b[1];
+            const d3 o = P - mk(b[2], b[3], b[4]);
+            const double e = A * exp(-dot(o, o) / (2.0 * s * s));
+            n += e;
+            g.x += -e * o.x / (s * s);
+            g.y += -e * o.y / (s * s);
+            g.z += -e * o.z / (s * s);
+        }
+    } else {  // GRID: trilinear n, trilinear node central differences
+        int c[3];
+        double f[3];
+        grid_cell64(m, P, c, f);
+        n = 0.0;
+        g = mk(0, 0, 0);
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    const double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *
+                                     (dz ? f[2] : 1.0 - f[2]);
+                    const int i = c[0] + dx, j = c[1] + dy, k = c[2] + dz;
+                    n += w * grid_node64(m, i, j, k);
+                    g.x += w * grid_cdiff64(m, i, j, k, 0);
+                    g.y += w * grid_cdiff64(m, i, j, k, 1);
+                    g.z += w * grid_cdiff64(m, i, j, k, 2);
+                }
+    }
+}
+
+template <int MK>
+__device__ __forceinline__ double index64(const MediumDev &m, d3 P) {
+    double n;
+    d3 g;
+    med64<MK>(m, P, n, g);
+    return n;
+}
+
+// ---------------------------------------------------------------------------
+// single precision with the index difference along the last move
+// ---------------------------------------------------------------------------
+struct MedF {  // single-precision constants of the analytic media
+    float q[8];
+};
+
+// expm1 on |x| <~ 0.2 by its Taylor polynomial (relative error < 2e-8 there);
+// the argument is the change of a bump exponent over one step.
+__device__ __forceinline__ float expm1_small(float x) {
+    return x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f +
+                                                                             x * (1.0f / 720.0f))))));
+}
+
+// P: point P_i, s = P_i - P_{i-1}, n_last = n(P_{i-1}).
+// MedF.q: LINEAR [n0, gx, gy, gz]; LUNEBURG [., cx, cy, cz, 1/R^2];
+// FIBER [n_c, Delta, ., cx, cy, 2 Delta n_c^2/R^2, n_clad, R^2]; others [n0]
+template <int MK>
+__device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf, f3 P, f3 s, float n_last,
+                                      float &n, f3 &g, float &dn) {
+    if constexpr (MK == VRT_MEDIUM_HOMOGENEOUS) {
+        n = mf.q[0];
+        g = mkf(0, 0, 0);
+        dn = 0.0f;
+    } else if constexpr (MK == VRT_MEDIUM_LINEAR) {
+        g = mkf(mf.q[1], mf.q[2], mf.q[3]);
+        n = mf.q[0] + dotf(g, P);
+        dn = dotf(g, s);
+    } else if constexpr (MK == VRT_MEDIUM_LUNEBURG) {
+        // n^2 = 2 - u, u = |P-C|^2/R^2:  n_i - n_{i-1} = -(u_i - u_{i-1}) / (n_i + n_{i-1}),
+        // u_i - u_{i-1} = (2 (P-C).s - |s|^2) / R^2
+        const f3 o = mkf(P.x - mf.q[1], P.y - mf.q[2], P.z - mf.q[3]);
+        const float u = dotf(o, o) * mf.q[4];
+        n = sqrtf(2.0f - u);
+        const float k = -mf.q[4] / n;
+        g = mkf(k * o.x, k * o.y, k * o.z);
+        const float du = (2.0f * dotf(o, s) - dotf(s, s)) * mf.q[4];
+        dn = -du / (n + n_last);
+    } else if constexpr (MK == VRT_MEDIUM_FIBER) {
+        const float x = P.x - mf.q[3], y = P.y - mf.q[4];
+        const float r2 = x * x + y * y;
+        const float xp = x - s.x, yp = y - s.y;
+        const bool core = r2 <= mf.q[7], core_p = xp * xp + yp * yp <= mf.q[7];
+        if (core) {
+            n = mf.q[0] * sqrtf(1.0f - 2.0f * mf.q[1] * r2 / mf.q[7]);
+            const float k = -mf.q[5] / n;
+            g = mkf(k * x, k * y, 0.0f);
+        } else {
+            n = mf.q[6];
+            g = mkf(0, 0, 0);
+        }
+        if (core && core_p) {
+            // n^2 difference: -(2 Delta n_c^2 / R^2) (2 (x s_x + y s_y) - s_x^2 - s_y^2)
+            const float d2 = 2.0f * (x * s.x + y * s.y) - (s.x * s.x + s.y * s.y);
+            dn = -mf.q[5] * d2 / (n + n_last);
+        } else {
+            dn = n - n_last;
+        }
+    } else if constexpr (MK == VRT_MEDIUM_GAUSSIAN) {
+        // E_k(P_{i-1}) = E_k(P_i) exp(dq_k), dq_k = ((P_i - c_k).s - |s|^2/2) / sigma^2,
+        // so n_i - n_{i-1} = -sum A_k E_k(P_i) expm1(dq_k).
+        float nn = mf.q[0], gx = 0.f, gy = 0.f, gz = 0.f, acc = 0.f;
+        const float hs2 = -0.5f * dotf(s, s);
+        const float *__restrict__ b = m.bumps_f;
+        const int K = m.K;
+#pragma unroll 4
+        for (int k = 0; k < K; ++k) {
+            const float A = b[kBumpF * k + 0], e2 = b[kBumpF * k + 1];
+            const float cx = b[kBumpF * k + 2], cy = b[kBumpF * k + 3], cz = b[kBumpF * k + 4];
+            const float is2 = b[kBumpF * k + 5];
+            const float ox = P.x - cx, oy = P.y - cy, oz = P.z - cz;
+            const float r2 = ox * ox + oy * oy + oz * oz;
+            const float e = A * __builtin_amdgcn_exp2f(r2 * e2);
+            nn += e;
+            const float w = e * is2;
+            gx -= w * ox;
+            gy -= w * oy;
+            gz -= w * oz;
+            const float dq = (ox * s.x + oy * s.y + oz * s.z + hs2) * is2;
+            acc -= e * expm1_small(dq);
+        }
+        n = nn;
+        g = mkf(gx, gy, gz);
+        dn = acc;
+    }
+}
+
+}  // namespace vrt

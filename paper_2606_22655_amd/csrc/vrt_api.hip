@@ -1,0 +1,565 @@
+// vrt_api.hip -- host side of libvrt: the extern "C" entry points declared
+// in include/vrt.h (contexts, device-resident media, trace dispatch, counter
+// reduction, error reporting).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dispatch.h"
+
+using namespace vrt;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+static int fail_hip(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? VRT_ENOMEM : VRT_EHIP, "%s: %s", what,
+                hipGetErrorString(e));
+}
+#define HIP_TRY(call, what)                                  \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return fail_hip(e_, (what));   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+static constexpr int kQueueSlots = 1024;
+static constexpr int kQueueStride = 16;  // uint32 per slot: one 64-byte line each
+static constexpr int kNumCounters = 15;
+
+struct vrt_context_s {
+    int device = 0;
+    int num_cu = 256;
+    uint32_t *queues = nullptr;  // kQueueSlots ray-queue counters
+    unsigned long long *counters = nullptr;
+    std::atomic<uint32_t> next_slot{0};
+    std::atomic<int> n_media{0};
+    std::mutex counters_mu;
+};
+
+struct vrt_medium_s {
+    vrt_context_t ctx = nullptr;
+    MediumDev dev{};
+    MedF mf{};
+    BoundaryDev bnd{};
+    size_t bytes = 0;
+    std::vector<void *> allocs;
+};
+
+static int set_device(vrt_context_t c) {
+    HIP_TRY(hipSetDevice(c->device), "hipSetDevice");
+    return VRT_OK;
+}
+
+static int dev_alloc(vrt_medium_t m, void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail_hip(e, "hipMalloc (medium)");
+    m->allocs.push_back(*p);
+    m->bytes += bytes;
+    return VRT_OK;
+}
+
+static void free_medium(vrt_medium_t m) {
+    for (void *p : m->allocs) (void)hipFree(p);
+    m->allocs.clear();
+    delete m;
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+// Node records of a discretized medium: value and, per axis, the central
+// difference of the node values divided by the number of spacings it spans
+// (2; 1 at the first and last node) -- exact in float for nearby values;
+// grad n = record * (1/h).  Flags non-positive or non-finite values.
+__global__ void grid_records_kernel(const float *__restrict__ v, float4 *__restrict__ rec, int nx,
+                                    int ny, int nz, unsigned int *bad) {
+    const size_t total = (size_t)nx * ny * nz;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx % nx);
+        const int j = (int)((idx / nx) % ny);
+        const int k = (int)(idx / ((size_t)nx * ny));
+        const float c = v[idx];
+        if (!(c > 0.0f) || !isfinite(c)) atomicOr(bad, 1u);
+        const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+        const int il = i > 0 ? i - 1 : 0, ih = i < nx - 1 ? i + 1 : nx - 1;
+        const int jl = j > 0 ? j - 1 : 0, jh = j < ny - 1 ? j + 1 : ny - 1;
+        const int kl = k > 0 ? k - 1 : 0, kh = k < nz - 1 ? k + 1 : nz - 1;
+        const size_t row = (size_t)k * sz + (size_t)j * sy;
+        const float hx = (v[row + ih] - v[row + il]) / (float)(ih - il);
+        const float hy = (v[(size_t)k * sz + (size_t)jh * sy + i] -
+                          v[(size_t)k * sz + (size_t)jl * sy + i]) / (float)(jh - jl);
+        const float hz = (v[(size_t)kh * sz + (size_t)j * sy + i] -
+                          v[(size_t)kl * sz + (size_t)j * sy + i]) / (float)(kh - kl);
+        rec[idx] = make_float4(c, hx, hy, hz);
+    }
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+__global__ void reduce_counters_kernel(const uint32_t *__restrict__ status,
+                                       const uint32_t *__restrict__ steps,
+                                       const uint32_t *__restrict__ ntir,
+                                       const uint32_t *__restrict__ nbtir,
+                                       const uint32_t *__restrict__ flags, size_t n,
+                                       unsigned long long *out) {
+    unsigned long long acc[kNumCounters] = {0};
+    for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t s = status[r], f = flags[r];
+        acc[0] += 1;
+        acc[1] += steps[r];
+        acc[2] += s == VRT_RAY_EXITED;
+        acc[3] += s == VRT_RAY_MISSED;
+        acc[4] += s == VRT_RAY_TRUNCATED;
+        acc[5] += s == VRT_RAY_NO_PLANE;
+        acc[6] += s == VRT_RAY_INVALID_INPUT;
+        acc[7] += s == VRT_RAY_REFLECTED_AT_ENTRY;
+        acc[8] += ntir[r];
+        acc[9] += nbtir[r];
+        acc[10] += (f & VRT_FLAG_NEAR_CRITICAL) != 0;
+        acc[11] += (f & VRT_FLAG_TANGENT) != 0;
+        acc[12] += (f & VRT_FLAG_STRAIGHT) != 0;
+        acc[13] += (f & VRT_FLAG_NEAR_TIE) != 0;
+        acc[14] += (f & VRT_FLAG_NEAR_GRAZING) != 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kNumCounters; ++k) {
+        unsigned long long v = acc[k];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+        if (__lane_id() == 0 && v) atomicAdd(out + k, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// API
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int vrt_abi_version(void) { return VRT_ABI_VERSION; }
+
+const char *vrt_last_error(void) { return g_err.c_str(); }
+
+int vrt_context_create(int hip_device, vrt_context_t *out) {
+    if (!out) return fail(VRT_EINVAL, "vrt_context_create: out is NULL");
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n), "hipGetDeviceCount");
+    if (hip_device < 0 || hip_device >= n)
+        return fail(VRT_EINVAL, "vrt_context_create: device %d of %d", hip_device, n);
+    HIP_TRY(hipSetDevice(hip_device), "hipSetDevice");
+    auto *c = new vrt_context_s();
+    c->device = hip_device;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, hip_device) ==
+            hipSuccess &&
+        cu > 0)
+        c->num_cu = cu;
+    hipError_t e = hipMalloc((void **)&c->queues, sizeof(uint32_t) * kQueueSlots * kQueueStride);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&c->counters, sizeof(unsigned long long) * kNumCounters);
+    if (e != hipSuccess) {
+        if (c->queues) (void)hipFree(c->queues);
+        delete c;
+        return fail_hip(e, "vrt_context_create: hipMalloc");
+    }
+    *out = c;
+    return VRT_OK;
+}
+
+int vrt_context_destroy(vrt_context_t ctx) {
+    if (!ctx) return fail(VRT_EINVAL, "vrt_context_destroy: NULL context");
+    if (ctx->n_media.load() != 0)
+        return fail(VRT_EINVAL, "vrt_context_destroy: %d media still alive", ctx->n_media.load());
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->queues);
+    (void)hipFree(ctx->counters);
+    delete ctx;
+    return VRT_OK;
+}
+
+static bool finite_all(const double *p, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(p[i])) return false;
+    return true;
+}
+
+static int check_boundary(const vrt_boundary *b, BoundaryDev &out) {
+    if (!b) return fail(VRT_EINVAL, "boundary is NULL");
+    if (b->reserved != 0) return fail(VRT_EINVAL, "boundary.reserved must be 0");
+    const double *p = b->params;
+    switch (b->kind) {
+    case VRT_BOUNDARY_BOX:
+        if (!finite_all(p, 6) || !(p[0] < p[3]) || !(p[1] < p[4]) || !(p[2] < p[5]))
+            return fail(VRT_EINVAL, "box boundary needs finite lo < hi");
+        break;
+    case VRT_BOUNDARY_SPHERE:
+        if (!finite_all(p, 4) || !(p[3] > 0.0)) return fail(VRT_EINVAL, "sphere radius must be > 0");
+        break;
+    case VRT_BOUNDARY_CYLINDER:
+        if (!finite_all(p, 5) || !(p[2] > 0.0) || !(p[3] < p[4]))
+            return fail(VRT_EINVAL, "cylinder needs r > 0 and z0 < z1");
+        break;
+    default:
+        return fail(VRT_EINVAL, "unknown boundary kind %d", b->kind);
+    }
+    out.kind = b->kind;
+    for (int i = 0; i < 6; ++i) {
+        out.p[i] = p[i];
+        out.pf[i] = (float)p[i];
+    }
+    return VRT_OK;
+}
+
+int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params, int n_params,
+                               const vrt_boundary *bnd, double n_ambient, vrt_medium_t *out) {
+    if (!ctx || !out) return fail(VRT_EINVAL, "vrt_medium_create_analytic: NULL argument");
+    if (!params || n_params <= 0 || !finite_all(params, n_params))
+        return fail(VRT_EINVAL, "vrt_medium_create_analytic: params missing or non-finite");
+    if (!(n_ambient > 0.0) || !isfinite(n_ambient))
+        return fail(VRT_EINVAL, "n_ambient must be finite and > 0");
+    static const int need[] = {1, 4, 4, 5, -1};
+    if (kind < VRT_MEDIUM_HOMOGENEOUS || kind > VRT_MEDIUM_GAUSSIAN)
+        return fail(kind == VRT_MEDIUM_GRID ? VRT_EINVAL : VRT_EINVAL,
+                    "analytic medium kind %d unknown (grids use vrt_medium_create_grid)", kind);
+    if (kind != VRT_MEDIUM_GAUSSIAN && n_params != need[kind])
+        return fail(VRT_EINVAL, "medium kind %d needs %d params, got %d", kind, need[kind], n_params);
+    BoundaryDev b;
+    if (int rc = check_boundary(bnd, b)) return rc;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    auto *m = new vrt_medium_s();
+    m->ctx = ctx;
+    m->bnd = b;
+    MediumDev &d = m->dev;
+    d.kind = kind;
+    d.n_amb = n_ambient;
+    const double *p = params;
+    MedF &f = m->mf;
+    switch (kind) {
+    case VRT_MEDIUM_HOMOGENEOUS:
+        if (!(p[0] > 0.0)) {
+            delete m;
+            return fail(VRT_EINVAL, "homogeneous index must be > 0");
+        }
+        d.q[0] = p[0];
+        f.q[0] = (float)p[0];
+        break;
+    case VRT_MEDIUM_LINEAR:
+        for (int i = 0; i < 4; ++i) {
+            d.q[i] = p[i];
+            f.q[i] = (float)p[i];
+        }
+        break;
+    case VRT_MEDIUM_LUNEBURG:
+        if (!(p[0] > 0.0)) {
+            delete m;
+            return fail(VRT_EINVAL, "Luneburg radius must be > 0");
+        }
+        for (int i = 0; i < 4; ++i) {
+            d.q[i] = p[i];
+            f.q[i] = (float)p[i];
+        }
+        f.q[4] = (float)(1.0 / (p[0] * p[0]));
+        break;
+    case VRT_MEDIUM_FIBER: {
+        const double nc = p[0], Dl = p[1], R = p[2];
+        if (!(nc > 0.0) || !(R > 0.0) || !(Dl >= 0.0) || !(2.0 * Dl < 1.0)) {
+            delete m;
+            return fail(VRT_EINVAL, "fiber needs n_c > 0, R > 0, 0 <= Delta < 1/2");
+        }
+        for (int i = 0; i < 5; ++i) {
+            d.q[i] = p[i];
+            f.q[i] = (float)p[i];
+        }
+        f.q[5] = (float)(2.0 * Dl * nc * nc / (R * R));
+        f.q[6] = (float)(nc * sqrt(1.0 - 2.0 * Dl));
+        f.q[7] = (float)(R * R);
+        break;
+    }
+    case VRT_MEDIUM_GAUSSIAN: {
+        if (n_params < 2) {
+            delete m;
+            return fail(VRT_EINVAL, "gaussian medium needs [n0, K, ...]");
+        }
+        const int K = (int)p[1];
+        if ((double)K != p[1] || K < 0 || K > VRT_MAX_BUMPS || n_params != 2 + 5 * K) {
+            delete m;
+            return fail(VRT_EINVAL, "gaussian medium: K=%g invalid or n_params %d != 2+5K", p[1],
+                        n_params);
+        }
+        d.q[0] = p[0];
+        f.q[0] = (float)p[0];
+        d.K = K;
+        std::vector<double> bd((size_t)kBumpD * (K > 0 ? K : 1), 0.0);
+        std::vector<float> bf((size_t)kBumpF * (K > 0 ? K : 1), 0.0f);
+        double amp = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double *q = p + 2 + 5 * k;
+            if (!(q[1] > 0.0)) {
+                delete m;
+                return fail(VRT_EINVAL, "gaussian bump %d: sigma must be > 0", k);
+            }
+            amp += fabs(q[0]);
+            for (int i = 0; i < 5; ++i) bd[(size_t)kBumpD * k + i] = q[i];
+            const double is2 = 1.0 / (q[1] * q[1]);
+            float *o = bf.data() + (size_t)kBumpF * k;
+            o[0] = (float)q[0];
+            o[1] = (float)(-0.5 * is2 / log(2.0));
+            o[2] = (float)q[2];
+            o[3] = (float)q[3];
+            o[4] = (float)q[4];
+            o[5] = (float)is2;
+        }
+        if (!(p[0] - amp > 0.0)) {
+            delete m;
+            return fail(VRT_EINVAL, "gaussian medium: n0 - sum|A| must be > 0");
+        }
+        void *pd = nullptr, *pf = nullptr;
+        if ((rc = dev_alloc(m, &pd, bd.size() * sizeof(double))) ||
+            (rc = dev_alloc(m, &pf, bf.size() * sizeof(float)))) {
+            free_medium(m);
+            return rc;
+        }
+        hipError_t e = hipMemcpy(pd, bd.data(), bd.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(pf, bf.data(), bf.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_medium(m);
+            return fail_hip(e, "hipMemcpy (gaussian params)");
+        }
+        d.bumps_d = (const double *)pd;
+        d.bumps_f = (const float *)pf;
+        break;
+    }
+    }
+    ctx->n_media++;
+    *out = m;
+    return VRT_OK;
+}
+
+int vrt_medium_create_grid(vrt_context_t ctx, const float *values, int nx, int ny, int nz,
+                           const double lo[3], const double hi[3], double n_ambient,
+                           int values_on_device, vrt_medium_t *out) {
+    if (!ctx || !out || !values || !lo || !hi)
+        return fail(VRT_EINVAL, "vrt_medium_create_grid: NULL argument");
+    if (nx < 2 || ny < 2 || nz < 2 || nx > 4096 || ny > 4096 || nz > 4096)
+        return fail(VRT_EINVAL, "grid dimensions must be in [2, 4096], got %d x %d x %d", nx, ny, nz);
+    if (!finite_all(lo, 3) || !finite_all(hi, 3) || !(lo[0] < hi[0]) || !(lo[1] < hi[1]) ||
+        !(lo[2] < hi[2]))
+        return fail(VRT_EINVAL, "grid extent needs finite lo < hi");
+    if (!(n_ambient > 0.0) || !isfinite(n_ambient))
+        return fail(VRT_EINVAL, "n_ambient must be finite and > 0");
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    auto *m = new vrt_medium_s();
+    m->ctx = ctx;
+    m->bnd.kind = VRT_BOUNDARY_BOX;
+    for (int a = 0; a < 3; ++a) {
+        m->bnd.p[a] = lo[a];
+        m->bnd.p[a + 3] = hi[a];
+    }
+    for (int i = 0; i < 6; ++i) m->bnd.pf[i] = (float)m->bnd.p[i];
+    MediumDev &d = m->dev;
+    d.kind = VRT_MEDIUM_GRID;
+    d.n_amb = n_ambient;
+    d.nx = nx;
+    d.ny = ny;
+    d.nz = nz;
+    const int nn[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) {
+        d.lo[a] = lo[a];
+        d.hi[a] = hi[a];
+        d.h[a] = (hi[a] - lo[a]) / (double)(nn[a] - 1);
+        d.inv_h[a] = 1.0 / d.h[a];
+        d.flo[a] = (float)lo[a];
+        d.fhi[a] = (float)hi[a];
+        d.finv_h[a] = (float)d.inv_h[a];
+    }
+    const size_t total = (size_t)nx * ny * nz;
+    void *g = nullptr, *r = nullptr, *bad = nullptr;
+    if ((rc = dev_alloc(m, &g, total * sizeof(float))) ||
+        (rc = dev_alloc(m, &r, total * sizeof(float4)))) {
+        free_medium(m);
+        return rc;
+    }
+    hipError_t e = hipMemcpy(g, values, total * sizeof(float),
+                             values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&bad, sizeof(unsigned int));
+    if (e == hipSuccess) e = hipMemset(bad, 0, sizeof(unsigned int));
+    if (e != hipSuccess) {
+        if (bad) (void)hipFree(bad);
+        free_medium(m);
+        return fail_hip(e, "vrt_medium_create_grid: copy");
+    }
+    size_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(grid_records_kernel, dim3((unsigned)blocks), dim3(256), 0, 0,
+                       (const float *)g, (float4 *)r, nx, ny, nz, (unsigned int *)bad);
+    unsigned int hbad = 0;
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost);
+    (void)hipFree(bad);
+    if (e != hipSuccess) {
+        free_medium(m);
+        return fail_hip(e, "vrt_medium_create_grid: records");
+    }
+    if (hbad) {
+        free_medium(m);
+        return fail(VRT_EINVAL, "grid values must be finite and > 0");
+    }
+    d.grid = (const float *)g;
+    d.rec = (const float4 *)r;
+    ctx->n_media++;
+    *out = m;
+    return VRT_OK;
+}
+
+int vrt_medium_destroy(vrt_medium_t m) {
+    if (!m) return fail(VRT_EINVAL, "vrt_medium_destroy: NULL medium");
+    vrt_context_t ctx = m->ctx;
+    (void)hipSetDevice(ctx->device);
+    hipError_t e = hipDeviceSynchronize();
+    free_medium(m);
+    ctx->n_media--;
+    if (e != hipSuccess) return fail_hip(e, "vrt_medium_destroy: device synchronize");
+    return VRT_OK;
+}
+
+int vrt_medium_device_bytes(vrt_medium_t m, size_t *out) {
+    if (!m || !out) return fail(VRT_EINVAL, "vrt_medium_device_bytes: NULL argument");
+    *out = m->bytes;
+    return VRT_OK;
+}
+
+static bool aligned(const void *p, size_t a) { return p && ((uintptr_t)p % a) == 0; }
+
+int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, size_t n_rays,
+              void *stream) {
+    if (!m || !p || !rays) return fail(VRT_EINVAL, "vrt_trace: NULL argument");
+    if (!(p->dL0 > 0.0) || !isfinite(p->dL0)) return fail(VRT_EINVAL, "vrt_trace: dL0 must be > 0");
+    if (p->max_steps <= 0 || p->max_steps > 0xFFFFFFFFll)
+        return fail(VRT_EINVAL, "vrt_trace: max_steps must be in [1, 2^32)");
+    if (p->reserved != 0) return fail(VRT_EINVAL, "vrt_trace: reserved must be 0");
+    if (!(p->eps_tan >= 0.0) || !(p->crit_rad >= 0.0) || !(p->tie_eps >= 0.0) ||
+        !(p->tie_eps <= 1e-6))
+        return fail(VRT_EINVAL, "vrt_trace: eps_tan, crit_rad >= 0 and tie_eps in [0, 1e-6]");
+    if (p->precision != VRT_FP64 && p->precision != VRT_FP32_COMP)
+        return fail(VRT_EINVAL, "vrt_trace: unknown precision %d", p->precision);
+    if (n_rays >= (1ull << 31)) return fail(VRT_EINVAL, "vrt_trace: n_rays must be < 2^31");
+    if (n_rays == 0) return VRT_OK;
+    const size_t es = p->precision == VRT_FP64 ? 8 : 4;
+    const void *ptrs[] = {rays->px, rays->py, rays->pz, rays->dx, rays->dy, rays->dz,
+                          rays->ox, rays->oy, rays->oz, rays->odx, rays->ody, rays->odz};
+    for (const void *q : ptrs)
+        if (!aligned(q, es)) return fail(VRT_EINVAL, "vrt_trace: ray array NULL or misaligned");
+    const void *uptrs[] = {rays->status, rays->steps, rays->n_tir, rays->n_btir, rays->flags};
+    for (const void *q : uptrs)
+        if (!aligned(q, 4)) return fail(VRT_EINVAL, "vrt_trace: result array NULL or misaligned");
+    vrt_context_t ctx = m->ctx;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    LaunchArgs a{};
+    a.m = m->dev;
+    a.mf = m->mf;
+    a.b = m->bnd;
+    a.t.dL0 = p->dL0;
+    a.t.max_steps = p->max_steps;
+    a.t.eps_tan = p->eps_tan;
+    a.t.crit_rad = p->crit_rad;
+    a.t.tie_eps = p->tie_eps;
+    a.t.has_plane = isnan(p->exit_plane_z) ? 0 : 1;
+    a.t.plane_z = a.t.has_plane ? p->exit_plane_z : 0.0;
+    a.n = (uint32_t)n_rays;
+    a.stream = (hipStream_t)stream;
+    a.num_cu = ctx->num_cu;
+    a.blocks_per_cu = 0;
+    hipError_t e;
+    if (p->precision == VRT_FP64) {
+        a.io64 = RaysDev<double>{(const double *)rays->px, (const double *)rays->py,
+                                 (const double *)rays->pz, (const double *)rays->dx,
+                                 (const double *)rays->dy, (const double *)rays->dz,
+                                 (double *)rays->ox, (double *)rays->oy, (double *)rays->oz,
+                                 (double *)rays->odx, (double *)rays->ody, (double *)rays->odz,
+                                 rays->status, rays->steps, rays->n_tir, rays->n_btir, rays->flags};
+        e = launch_march_fp64(a);
+    } else {
+        a.io32 = RaysDev<float>{(const float *)rays->px, (const float *)rays->py,
+                                (const float *)rays->pz, (const float *)rays->dx,
+                                (const float *)rays->dy, (const float *)rays->dz,
+                                (float *)rays->ox, (float *)rays->oy, (float *)rays->oz,
+                                (float *)rays->odx, (float *)rays->ody, (float *)rays->odz,
+                                rays->status, rays->steps, rays->n_tir, rays->n_btir, rays->flags};
+        const uint32_t slot = ctx->next_slot.fetch_add(1) % kQueueSlots;
+        a.queue = ctx->queues + (size_t)slot * kQueueStride;
+        e = launch_march_fp32c(a);
+    }
+    if (e != hipSuccess) return fail_hip(e, "vrt_trace: launch");
+    return VRT_OK;
+}
+
+int vrt_reduce_counters(vrt_context_t ctx, const vrt_rays *rays, size_t n_rays, vrt_counters *out,
+                        void *stream) {
+    if (!ctx || !rays || !out) return fail(VRT_EINVAL, "vrt_reduce_counters: NULL argument");
+    if (n_rays > 0 && (!aligned(rays->status, 4) || !aligned(rays->steps, 4) ||
+                       !aligned(rays->n_tir, 4) || !aligned(rays->n_btir, 4) ||
+                       !aligned(rays->flags, 4)))
+        return fail(VRT_EINVAL, "vrt_reduce_counters: result array NULL or misaligned");
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ctx->counters_mu);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long h[kNumCounters] = {0};
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, ctx->counters, kNumCounters);
+    if (n_rays > 0) {
+        size_t blocks = (n_rays + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(reduce_counters_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                           rays->status, rays->steps, rays->n_tir, rays->n_btir, rays->flags,
+                           n_rays, ctx->counters);
+    }
+    HIP_TRY(hipGetLastError(), "vrt_reduce_counters: launch");
+    HIP_TRY(hipMemcpyAsync(h, ctx->counters, sizeof h, hipMemcpyDeviceToHost, s),
+            "vrt_reduce_counters: copy");
+    HIP_TRY(hipStreamSynchronize(s), "vrt_reduce_counters: synchronize");
+    out->rays = h[0];
+    out->steps = h[1];
+    out->exited = h[2];
+    out->missed = h[3];
+    out->truncated = h[4];
+    out->no_plane = h[5];
+    out->invalid = h[6];
+    out->reflected_at_entry = h[7];
+    out->tir_interior = h[8];
+    out->tir_boundary = h[9];
+    out->flagged_near_critical = h[10];
+    out->tangent = h[11];
+    out->straight = h[12];
+    out->flagged_near_tie = h[13];
+    out->flagged_near_grazing = h[14];
+    return VRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,365 @@
+"""GPU parity: the HIP march through the C ABI against the FP64 oracle on the
+same seeded inputs, element by element.
+
+FP64 path: identical discrete decisions (status, steps, TIR counts, flags)
+and exit states within 1e-9.  FP32 compensated path: the bar of
+tests/parity.py (1e-4 x aperture, 1e-4 rad, identical TIR/exit counts
+outside oracle-flagged near-critical rays).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from parity import (assert_parity, assert_stats, compare, exempt, ill_conditioned,
+                    stat_compare)
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def vrt():
+    import torch
+
+    import paper_2606_22655_amd as vrt
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    vrt.load_library()
+    return vrt
+
+
+@pytest.fixture(scope="module")
+def ctx(vrt):
+    c = vrt.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(vrt, ctx, spec, rays, params, precision):
+    import torch
+
+    med = vrt.Medium(ctx, spec)
+    try:
+        b = vrt.RayBatch(rays[0], rays[1], precision)
+        vrt.trace(med, b, params, precision)
+        torch.cuda.synchronize()
+        return b.results()
+    finally:
+        med.close()
+
+
+def report(name, rep):
+    print(f"\n[parity] {name}: " + json.dumps({k: v for k, v in rep.items() if k != "bad_rays"}),
+          flush=True)
+
+
+def tight(orc, gpu, tol=1e-9):
+    for k in ("status", "steps", "ntir", "nbtir", "flags"):
+        assert np.array_equal(orc[k], gpu[k]), (k, np.nonzero(orc[k] != gpu[k])[0][:10])
+    assert np.abs(orc["P"] - gpu["P"]).max() < tol
+    assert np.abs(orc["D"] - gpu["D"]).max() < tol
+
+
+# ---------------------------------------------------------------------------
+# Luneburg sphere, parallel beam (plain FP64 configuration: all 4096 rays)
+# ---------------------------------------------------------------------------
+def test_luneburg_fp64_all_rays(vrt, ctx, orc):
+    spec, rays, prm = workloads.luneburg_beam()
+    o = orc.trace(spec, rays, prm)
+    g = run_gpu(vrt, ctx, spec, rays, prm, "fp64")
+    report("luneburg fp64", compare(o, g, aperture=2.0))
+    tight(o, g, tol=1e-12)
+
+
+def test_luneburg_fp32c_all_rays(vrt, ctx, orc):
+    spec, rays, prm = workloads.luneburg_beam()
+    o = orc.trace(spec, rays, prm)
+    g = run_gpu(vrt, ctx, spec, rays, prm, "fp32c")
+    rep = compare(o, g, aperture=2.0)
+    report("luneburg fp32c", rep)
+    assert_parity(rep)
+
+
+# ---------------------------------------------------------------------------
+# freeform analytic medium (16 Gaussian bumps in the unit cube)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def gauss_case(orc):
+    spec, (P0, d0), prm = workloads.gaussian_cube(n_rays=1 << 14)
+    o = orc.trace(spec, (P0, d0), prm)
+    return spec, (P0, d0), prm, o
+
+
+def test_gaussian_fp64(vrt, ctx, gauss_case):
+    spec, rays, prm, o = gauss_case
+    g = run_gpu(vrt, ctx, spec, rays, prm, "fp64")
+    report("gaussian fp64", compare(o, g, aperture=1.0))
+    tight(o, g, tol=1e-8)
+
+
+def test_gaussian_fp32c(vrt, ctx, gauss_case):
+    spec, rays, prm, o = gauss_case
+    g = run_gpu(vrt, ctx, spec, rays, prm, "fp32c")
+    rep = compare(o, g, aperture=1.0)
+    report("gaussian fp32c", rep)
+    assert_parity(rep)
+
+
+# ---------------------------------------------------------------------------
+# discretized isoindicial medium (quantized 256^3 grid)
+#
+# This medium is chaotic for the discrete march: shifting launch points by
+# 1e-11 already moves most of the oracle's own exits by more than 1e-4.  So:
+#   FP64 path: the same IEEE-double evaluation as the oracle -> identical;
+#   FP32 path: per-ray parity over the first 128 moves of every ray (before
+#   the divergence of neighbouring rays has grown), except the few rays whose
+#   oracle state is itself unstable under a 1e-9 launch shift (counted), and
+#   agreement of the exit-state statistics over full paths.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def grid_case(orc):
+    spec = workloads.grid_medium(workloads.noise_grid(256, 3))
+    P0, d0 = workloads.face_cone_rays(1 << 13, 103, 30.0)
+    prm = workloads.trace_params(5e-4, 60000)
+    o = orc.trace(spec, (P0, d0), prm)
+    return spec, (P0, d0), prm, o
+
+
+def test_grid_fp64_identical(vrt, ctx, grid_case):
+    spec, rays, prm, o = grid_case
+    g = run_gpu(vrt, ctx, spec, rays, prm, "fp64")
+    report("grid fp64", compare(o, g, aperture=1.0))
+    tight(o, g, tol=1e-12)
+
+
+def test_grid_fp32c_truncated_march(vrt, ctx, orc, grid_case):
+    spec, rays, prm, _ = grid_case
+    p128 = dict(prm)
+    p128["max_steps"] = 128
+    o = orc.trace(spec, rays, p128)
+    g = run_gpu(vrt, ctx, spec, rays, p128, "fp32c")
+    bad = ill_conditioned(orc.trace, spec, rays, p128)
+    rep = compare(exempt(o, bad), exempt(g, bad), aperture=1.0)
+    rep["ill_conditioned"] = int(bad.sum())
+    report("grid fp32c first 128 moves", rep)
+    assert bad.sum() <= 0.01 * len(bad)
+    assert_parity(rep)
+
+
+def test_grid_fp32c_statistics(vrt, ctx, grid_case):
+    spec, rays, prm, o = grid_case
+    g = run_gpu(vrt, ctx, spec, rays, prm, "fp32c")
+    rep = stat_compare(o, g)
+    print("\n[stats] grid fp32c full paths: " + json.dumps(rep), flush=True)
+    assert_stats(rep)
+
+
+# ---------------------------------------------------------------------------
+# the paper's helix (one ray, 808k steps) and other media / surfaces
+# ---------------------------------------------------------------------------
+def helix_case():
+    nc, Dl, R, rho0 = 1.38, 0.2, 5.0, 4.0
+    ncl = nc * math.sqrt(1 - 2 * Dl)
+    om = nc * math.sqrt(2 * Dl) / R
+    s = om * rho0 / ncl
+    spec = {"kind": "fiber", "params": np.array([nc, Dl, R, 0.0, 0.0]),
+            "boundary": {"kind": "cylinder", "params": np.array([0, 0, R, 0.0, 55.0])},
+            "n_amb": ncl}
+    d0 = np.array([[0.0, s, math.sqrt(1 - s * s)]])
+    P0 = np.array([[4.0, 0.0, 0.0]]) - rho0 * d0
+    return spec, (P0, d0), workloads.trace_params(1e-4, 2_000_000)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_helix(vrt, ctx, orc, precision):
+    spec, rays, prm = helix_case()
+    if precision == "fp32c":  # inputs as the float32 path sees them
+        rays = (rays[0].astype(np.float32).astype(np.float64),
+                rays[1].astype(np.float32).astype(np.float64))
+    o = orc.trace(spec, rays, prm)
+    g = run_gpu(vrt, ctx, spec, rays, prm, precision)
+    rep = compare(o, g, aperture=10.0)
+    report(f"helix {precision}", rep)
+    if precision == "fp64":
+        tight(o, g, tol=1e-9)
+    else:
+        assert rep["status_mismatch"] == 0 and rep["pos_fail"] == 0 and rep["dir_fail"] == 0
+
+
+MEDIA = {
+    "homogeneous_sphere": ({"kind": "homogeneous", "params": np.array([1.5]),
+                            "boundary": {"kind": "sphere", "params": np.array([0.5, 0.5, 0.5, 0.5])},
+                            "n_amb": 1.0}, 1.0),
+    "linear_box": ({"kind": "linear", "params": np.array([1.5, 0.1, -0.2, 0.3]),
+                    "boundary": {"kind": "box", "params": np.array([0, 0, 0, 1, 1, 1.0])},
+                    "n_amb": 1.0}, 1.0),
+    "luneburg_offset": ({"kind": "luneburg", "params": np.array([0.5, 0.5, 0.5, 0.5]),
+                         "boundary": {"kind": "sphere", "params": np.array([0.5, 0.5, 0.5, 0.5])},
+                         "n_amb": 1.0}, 1.0),
+    "fiber_cylinder": ({"kind": "fiber", "params": np.array([1.45, 0.1, 0.5, 0.5, 0.5]),
+                        "boundary": {"kind": "cylinder", "params": np.array([0.5, 0.5, 0.5, 0.0, 1.0])},
+                        "n_amb": 1.0}, 1.0),
+    "dense_surroundings": ({"kind": "homogeneous", "params": np.array([1.2]),
+                            "boundary": {"kind": "box", "params": np.array([0, 0, 0, 1, 1, 1.0])},
+                            "n_amb": 1.6}, 1.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MEDIA))
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_media_and_surfaces(vrt, ctx, orc, name, precision):
+    spec, ap = MEDIA[name]
+    P0, d0 = workloads.face_cone_rays(1000, seed=77, cone_deg=60.0)  # ragged: not a multiple of 64
+    prm = workloads.trace_params(1e-3, 50000)
+    o = orc.trace(spec, (P0, d0), prm)
+    g = run_gpu(vrt, ctx, spec, (P0, d0), prm, precision)
+    rep = compare(o, g, aperture=ap)
+    report(f"{name} {precision}", rep)
+    if precision == "fp64":
+        tight(o, g, tol=1e-9)
+    else:
+        assert_parity(rep)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_edge_cases(vrt, ctx, orc, precision):
+    spec = {"kind": "homogeneous", "params": np.array([1.5]),
+            "boundary": {"kind": "sphere", "params": np.array([0.0, 0.0, 0.0, 1.0])}, "n_amb": 1.0}
+    P0 = np.array([[0, 0, -3.0], [3, 3, -3.0], [np.nan, 0, 0], [0, 0, -3.0], [0, 0, 0.0],
+                   [0.2, 0.1, 0.3]])
+    d0 = np.array([[0, 0, 1.0], [0, 0, 1.0], [0, 0, 1.0], [0, 0, 0.0], [1.0, 0, 0],
+                   [0.3, -0.2, 0.9]])
+    prm = workloads.trace_params(1e-3, 10000)
+    o = orc.trace(spec, (P0, d0), prm)
+    g = run_gpu(vrt, ctx, spec, (P0, d0), prm, precision)
+    assert list(g["status"]) == [0, 1, 4, 4, 0, 0]
+    assert np.array_equal(o["status"], g["status"])
+    ok = o["status"] == 0
+    assert np.allclose(o["P"][ok], g["P"][ok], atol=1e-6)
+    # truncation
+    prm5 = workloads.trace_params(1e-3, 5)
+    g = run_gpu(vrt, ctx, spec, (P0[:1], d0[:1]), prm5, precision)
+    assert g["status"][0] == 2 and g["steps"][0] == 5
+    # exit plane
+    box = {"kind": "homogeneous", "params": np.array([1.5]),
+           "boundary": {"kind": "box", "params": np.array([0, 0, 0, 1, 1, 1.0])}, "n_amb": 1.0}
+    Pc, dc = workloads.face_cone_rays(300, seed=5, cone_deg=10.0)
+    prmp = workloads.trace_params(1e-3, 10000, exit_plane_z=1.2)
+    o = orc.trace(box, (Pc, dc), prmp)
+    g = run_gpu(vrt, ctx, box, (Pc, dc), prmp, precision)
+    assert np.array_equal(o["status"], g["status"])
+    assert np.abs(o["P"] - g["P"]).max() < 1e-5
+    # empty batch is a no-op
+    g = run_gpu(vrt, ctx, box, (Pc[:0], dc[:0]), prmp, precision)
+    assert len(g["status"]) == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_tangential_rule_meridional_ray(vrt, ctx, orc, precision):
+    spec = {"kind": "fiber", "params": np.array([1.38, 0.2, 5.0, 0.0, 0.0]),
+            "boundary": {"kind": "cylinder", "params": np.array([0, 0, 5.0, 0.0, 10.0])},
+            "n_amb": 1.0}
+    P0 = np.array([[2.0, 0.0, 1.0], [-1.5, 0.0, 2.0], [0.0, 3.0, 0.5]])
+    d0 = np.array([[0, 0, 1.0], [0, 0, 1.0], [0, 0, 1.0]])
+    prm = workloads.trace_params(1e-3, 200000)
+    o = orc.trace(spec, (P0, d0), prm)
+    g = run_gpu(vrt, ctx, spec, (P0, d0), prm, precision)
+    assert np.all(o["flags"] & 2) and np.all(g["flags"] & 2)
+    rep = compare(o, g, aperture=10.0)
+    report(f"meridional {precision}", rep)
+    assert rep["status_mismatch"] == 0 and rep["pos_fail"] == 0 and rep["dir_fail"] == 0
+
+
+def test_counters_match_outputs(vrt, ctx):
+    import torch
+
+    spec, (P0, d0), prm = workloads.gaussian_cube(n_rays=5000)
+    med = vrt.Medium(ctx, spec)
+    try:
+        b = vrt.RayBatch(P0, d0, "fp32c")
+        vrt.trace(med, b, prm, "fp32c")
+        c = vrt.counters(ctx, b)
+        r = b.results()
+    finally:
+        med.close()
+    assert c["rays"] == 5000
+    assert c["steps"] == int(r["steps"].sum())
+    assert c["exited"] == int((r["status"] == 0).sum())
+    assert c["tir_interior"] == int(r["ntir"].sum())
+    assert c["tir_boundary"] == int(r["nbtir"].sum())
+    assert c["flagged_near_critical"] == int(((r["flags"] & 1) != 0).sum())
+
+
+def test_alone_equals_in_batch_bitwise(vrt, ctx):
+    """A ray's result does not depend on which lane, wave or batch runs it."""
+    spec, (P0, d0), prm = workloads.gaussian_cube(n_rays=3000)
+    full = run_gpu(vrt, ctx, spec, (P0, d0), prm, "fp32c")
+    idx = np.array([0, 17, 1234, 2999])
+    alone = run_gpu(vrt, ctx, spec, (P0[idx], d0[idx]), prm, "fp32c")
+    perm = np.random.default_rng(1).permutation(3000)
+    shuf = run_gpu(vrt, ctx, spec, (P0[perm], d0[perm]), prm, "fp32c")
+    inv = np.argsort(perm)
+    for k in ("P", "D", "status", "steps", "ntir", "nbtir", "flags"):
+        assert np.array_equal(full[k][idx], alone[k]), k
+        assert np.array_equal(full[k], shuf[k][inv]), k
+
+
+def test_full_size_sampled_parity(vrt, ctx, orc):
+    """The 1M-ray freeform configuration in the launch configuration the
+    benchmark times; the oracle recomputes a seeded sample of 1024 rays."""
+    spec, (P0, d0), prm = workloads.gaussian_cube()
+    g = run_gpu(vrt, ctx, spec, (P0, d0), prm, "fp32c")
+    n = P0.shape[0]
+    # properties at any size
+    ok = g["status"] == 0
+    assert ok.mean() > 0.99
+    assert np.allclose(np.linalg.norm(g["D"][ok], axis=1), 1.0, atol=1e-5)
+    onface = np.min(np.minimum(np.abs(g["P"][ok]), np.abs(g["P"][ok] - 1.0)), axis=1)
+    assert onface.max() < 1e-6
+    idx = np.sort(np.random.default_rng(2024).choice(n, 1024, replace=False))
+    o = orc.trace(spec, (P0[idx], d0[idx]), prm)
+    sub = {k: v[idx] for k, v in g.items()}
+    rep = compare(o, sub, aperture=1.0)
+    report("gaussian fp32c full-size sample", rep)
+    assert_parity(rep)
+
+
+def test_api_errors(vrt, ctx):
+    import torch
+
+    spec, (P0, d0), prm = workloads.gaussian_cube(n_rays=64)
+    med = vrt.Medium(ctx, spec)
+    try:
+        b = vrt.RayBatch(P0, d0, "fp32c")
+        bad = dict(prm)
+        bad["dL0"] = -1.0
+        with pytest.raises(vrt.VrtError) as e:
+            vrt.trace(med, b, bad, "fp32c")
+        assert e.value.code == vrt.VRT_EINVAL and "dL0" in vrt.vrt_last_error()
+        with pytest.raises(vrt.VrtError):
+            vrt.trace(med, b, prm, 7)
+        bad = dict(prm)
+        bad["max_steps"] = 0
+        with pytest.raises(vrt.VrtError):
+            vrt.trace(med, b, bad, "fp32c")
+        # misaligned pointer
+        saved = b.rays.px
+        b.rays.px = saved + 2
+        with pytest.raises(vrt.VrtError):
+            vrt.trace(med, b, prm, "fp32c")
+        b.rays.px = saved
+        with pytest.raises(vrt.VrtError):  # context with a live medium
+            vrt.vrt_context_destroy(ctx.handle)
+    finally:
+        med.close()
+    with pytest.raises(vrt.VrtError):
+        vrt.Medium(ctx, {"kind": "gaussian", "params": np.array([1.5, 2.0, 0.1]),
+                         "boundary": {"kind": "box", "params": np.zeros(6)}, "n_amb": 1.0})
+    with pytest.raises(vrt.VrtError):
+        vrt.Medium(ctx, workloads.grid_medium(-np.ones((3, 3, 3), np.float32)))
+    torch.cuda.synchronize()
