@@ -116,10 +116,10 @@ def cpu_baseline(spec, rays, prm, sample, g_res, aperture):
     from parity import compare
 
     sub = {k: v[:n] for k, v in g_res.items()}
-    rep = compare(r, sub, aperture=aperture)
+    rep = compare(r, sub, aperture=aperture, spec=spec)
     keys = ("n", "flagged_oracle", "flagged_gpu", "status_mismatch", "tir_mismatch",
             "btir_mismatch", "pos_fail", "dir_fail", "steps_mismatch", "pos_err_max", "pos_err_p99",
-            "dir_err_max", "dir_err_p99")
+            "dir_err_max", "dir_err_p99", "dir_err_inside_max")
     return base, {k: rep[k] for k in keys}
 
 
@@ -130,7 +130,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="freeform", choices=["freeform", "grid", "luneburg"])
     ap.add_argument("--rays", type=int, default=None)
-    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--cpu-sample", type=int, default=524288)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-gpu", action="store_true")
     args = ap.parse_args(argv)

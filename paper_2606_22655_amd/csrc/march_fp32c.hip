@@ -269,6 +269,17 @@ __device__ bool lane_init(const MediumDev &m, const BoundaryDev &b, const TraceD
     return true;
 }
 
+// Restore |I| = 1 against the drift of rounding in the increments.  Called
+// for the whole wave at once (every 64 iterations), so the double-precision
+// work is not repeated for each lane's own schedule.
+__device__ __forceinline__ void lane_renorm(Lane &L) {
+    d3 I = mk((double)L.Ihx - L.Icx, (double)L.Ihy - L.Icy, (double)L.Ihz - L.Icz);
+    I = (1.0 / sqrt(dot(I, I))) * I;
+    split(I.x, L.Ihx, L.Icx);
+    split(I.y, L.Ihy, L.Icy);
+    split(I.z, L.Ihz, L.Icz);
+}
+
 // One decision (unless pending) and one move.  Returns false when the ray
 // ended (written).
 template <int MK>
@@ -293,7 +304,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
         float incx = 0.f, incy = 0.f, incz = 0.f, Delta;
         const float gl2 = gx * gx + gy * gy + gz * gz;
         if (!(gl2 > 0.0f) || !isfinite(gl2)) {  // cases (ii)/(iii): straight
-            Delta = dL0 / ni;
+            Delta = dL0 * frcp(ni);
             L.flags |= VRT_FLAG_STRAIGHT;
         } else {
             const float inv = rsqrtf(gl2);
@@ -303,7 +314,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
             if (fabsf(c) <= eps_tan) {
                 // case (iv): arc with curvature grad n / n, Eqs. (16)-(18);
                 // dn along the probe Delta N in difference form
-                Delta = dL0 / ni;
+                Delta = dL0 * frcp(ni);
                 const float qx = Delta * Nx, qy = Delta * Ny, qz = Delta * Nz;
                 float np, dnp;
                 if constexpr (MK == VRT_MEDIUM_GRID) {
@@ -317,15 +328,15 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
                     med32<MK>(m, mf, mkf(L.Phx + qx, L.Phy + qy, L.Phz + qz), mkf(qx, qy, qz), ni,
                               np, gp, dnp);
                 }
-                const float a = dnp / (2.0f * ni);
-                const float w = sqrtf(fmaxf(0.0f, 1.0f - a * a));
+                const float a = dnp * frcp(2.0f * ni);
+                const float w = fsqrt(fmaxf(0.0f, 1.0f - a * a));
                 const float k = -a * a / (1.0f + w);  // sqrt(1-a^2) - 1 without cancellation
                 incx = k * L.Ihx + a * Nx;
                 incy = k * L.Ihy + a * Ny;
                 incz = k * L.Ihz + a * Nz;
                 L.flags |= VRT_FLAG_TANGENT;
             } else {
-                const float m1 = -dn / ni;  // mu_i - 1, mu_i = n_{i-1} / n_i
+                const float m1 = -dn * frcp(ni);  // mu_i - 1, mu_i = n_{i-1} / n_i
                 if (c * c <= 4.0f * fabsf(m1) * (2.0f + m1)) {
                     // near grazing: the step is taken in double -- n at P_i and
                     // P_{i-1}, the normal, c, D and R (Eqs. (5), (9)-(10), (19)-(20))
@@ -369,13 +380,13 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
                     if (m1 > 0.0f && fabs(D) < 2.0 * mu * mu * t.crit_rad &&
                         near_critical(mu, cd, D, t.crit_rad))
                         L.flags |= VRT_FLAG_NEAR_CRITICAL;
-                    const float sD = sqrtf((float)D);
-                    const float q = m1 * (2.0f + m1) / (sD + (1.0f + m1) * fabsf(c));
+                    const float sD = fsqrt((float)D);
+                    const float q = m1 * (2.0f + m1) * frcp(sD + (1.0f + m1) * fabsf(c));
                     const float gam = c > 0.0f ? -q : q;  // -sgn(c) q, q signed
                     incx = m1 * L.Ihx + gam * Nx;
                     incy = m1 * L.Ihy + gam * Ny;
                     incz = m1 * L.Ihz + gam * Nz;
-                    Delta = dL0 / ni;
+                    Delta = dL0 * frcp(ni);
                 }
             }
         }
@@ -385,13 +396,6 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
         kahan_add(L.Ihy, L.Icy, incy);
         kahan_add(L.Ihz, L.Icz, incz);
         L.Delta = Delta;
-        if ((L.steps & 63u) == 63u) {  // keep |I| = 1 (rounding drift only)
-            d3 I = mk((double)L.Ihx - L.Icx, (double)L.Ihy - L.Icy, (double)L.Ihz - L.Icz);
-            I = (1.0 / sqrt(dot(I, I))) * I;
-            split(I.x, L.Ihx, L.Icx);
-            split(I.y, L.Ihy, L.Icy);
-            split(I.z, L.Ihz, L.Icz);
-        }
     }
     L.pending = false;
     // ---- move (Eqs. (3)-(4)), cut at the enclosing surface (case (i)) ----
@@ -471,10 +475,26 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
     return false;
 }
 
+// Everything a launch reads, passed as one kernel argument and read through a
+// pointer: the fields of the rare paths are then loaded when used instead of
+// being held in scalar registers for the whole kernel.
+struct Launch32 {
+    MediumDev m;
+    MedF mf;
+    BoundaryDev b;
+    TraceDev t;
+    RaysDev<float> io;
+};
+
 template <int MK>
-__global__ __launch_bounds__(256) void march_fp32c_kernel(MediumDev m, MedF mf, BoundaryDev b,
-                                                          TraceDev t, RaysDev<float> io, uint32_t n,
+__global__ __launch_bounds__(256) void march_fp32c_kernel(Launch32 desc, uint32_t n,
                                                           uint32_t *queue) {
+    const Launch32 *__restrict__ D = &desc;
+    const MediumDev &m = D->m;
+    const MedF &mf = D->mf;
+    const BoundaryDev &b = D->b;
+    const TraceDev &t = D->t;
+    const RaysDev<float> &io = D->io;
     Lane L;
     GridCache gc;
     gc.ci = -1;
@@ -484,6 +504,7 @@ __global__ __launch_bounds__(256) void march_fp32c_kernel(MediumDev m, MedF mf, 
     // a step whose end is this far inside cannot be within tie_eps of a cut
     const float mrg = fmaxf(2e-6f, 4.0f * (float)t.tie_eps);
     const int lane = __lane_id();
+    uint32_t it = 0;  // iterations of the wave (uniform)
     for (;;) {
         const bool need = !active && !done;
         const uint64_t nm = __ballot(need);
@@ -507,6 +528,7 @@ __global__ __launch_bounds__(256) void march_fp32c_kernel(MediumDev m, MedF mf, 
             continue;
         }
         if (active) active = lane_step<MK>(m, mf, b, t, io, L, gc, dL0, eps_tan, mrg);
+        if ((++it & 63u) == 0u && active) lane_renorm(L);
     }
 }
 
@@ -528,8 +550,9 @@ static hipError_t launch32(const LaunchArgs &a) {
     const uint32_t need = (a.n + 255u) / 256u;
     if (blocks > need) blocks = need;
     hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, a.stream, a.queue);
-    hipLaunchKernelGGL(march_fp32c_kernel<MK>, dim3(blocks), dim3(256), 0, a.stream, a.m, a.mf, a.b,
-                       a.t, a.io32, a.n, a.queue);
+    const Launch32 desc{a.m, a.mf, a.b, a.t, a.io32};
+    hipLaunchKernelGGL(march_fp32c_kernel<MK>, dim3(blocks), dim3(256), 0, a.stream, desc, a.n,
+                       a.queue);
     return hipGetLastError();
 }
 

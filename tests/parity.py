@@ -28,8 +28,74 @@ def angle_between(a, b):
     return 2.0 * np.arcsin(np.clip(np.linalg.norm(a - b, axis=1) / 2.0, 0.0, 1.0))
 
 
-def compare(orc, gpu, aperture, pos_tol=1e-4, dir_tol=1e-4):
+def surface_normal(boundary, P, tol=1e-7):
+    """Outward unit normal of the enclosing surface at points P (m,3) lying on
+    it; NaN rows where a point is not on the surface within tol."""
+    kind, q = boundary["kind"], np.asarray(boundary["params"], dtype=np.float64)
+    N = np.full(P.shape, np.nan)
+    if kind == "sphere":
+        o = P - q[:3]
+        r = np.linalg.norm(o, axis=1)
+        on = np.abs(r - q[3]) < tol
+        N[on] = o[on] / r[on, None]
+    elif kind == "box":
+        lo, hi = q[:3], q[3:6]
+        for a in range(3):
+            for side, val in ((-1.0, lo[a]), (1.0, hi[a])):
+                on = np.abs(P[:, a] - val) < tol
+                N[on] = 0.0
+                N[on, a] = side
+    elif kind == "cylinder":
+        cx, cy, r0, z0, z1 = q[:5]
+        o = P[:, :2] - np.array([cx, cy])
+        r = np.linalg.norm(o, axis=1)
+        side = np.abs(r - r0) < tol
+        N[side, :2] = o[side] / r[side, None]
+        N[side, 2] = 0.0
+        for sgn, zz in ((-1.0, z0), (1.0, z1)):
+            cap = np.abs(P[:, 2] - zz) < tol
+            N[cap] = np.array([0.0, 0.0, sgn])
+    return N
+
+
+def exit_gain(spec, orc, n_index):
+    """How much the final refraction out of the medium magnifies an error of
+    the direction inside.  Snell's law n_in sin t_in = n_amb sin t_out (the
+    scalar form of Eqs. (9)-(10)) differentiates to
+    d t_out / d t_in = n_in cos t_in / (n_amb cos t_out); near the critical
+    angle cos t_out -> 0 and a direction that is 1e-6 rad off inside leaves
+    the surface 1e-4 rad off.  n_index(P) gives n at the exit points.
+    Returns the factor (>= 1) per ray, 1 where the exit point is not on the
+    enclosing surface (an exit plane) or the ray did not leave."""
+    gain = np.ones(len(orc["status"]))
+    ex = orc["status"] == 0
+    if not ex.any():
+        return gain
+    P, D = orc["P"][ex], orc["D"][ex]
+    N = surface_normal(spec["boundary"], P)
+    ok = np.isfinite(N).all(axis=1)
+    if not ok.any():
+        return gain
+    cos_out = np.abs(np.einsum("ij,ij->i", D[ok], N[ok]) /
+                     np.linalg.norm(D[ok], axis=1))
+    mu = n_index(P[ok]) / spec["n_amb"]
+    sin2_out = 1.0 - cos_out ** 2
+    mu_cos_in = np.sqrt(np.maximum(mu ** 2 - sin2_out, 0.0))
+    g = mu_cos_in / np.maximum(cos_out, 1e-12)
+    idx = np.nonzero(ex)[0][ok]
+    gain[idx] = np.maximum(1.0, g)
+    return gain
+
+
+def compare(orc, gpu, aperture, pos_tol=1e-4, dir_tol=1e-4, spec=None):
+    """spec (the medium) given: the exit direction's bar is dir_tol times the
+    exit refraction's gain (exit_gain), i.e. dir_tol on the direction inside."""
     n = len(orc["status"])
+    dir_gain = None
+    if spec is not None:
+        import oracle
+
+        dir_gain = exit_gain(spec, orc, lambda P: oracle.evaluate(spec, P)[0])
     ex_o = (orc["flags"] & EXEMPT) != 0
     ex_g = (gpu["flags"] & EXEMPT) != 0
     keep = ~ex_o
@@ -40,7 +106,8 @@ def compare(orc, gpu, aperture, pos_tol=1e-4, dir_tol=1e-4):
     de = angle_between(orc["D"], gpu["D"])
     same = keep & st
     bad_pos = same & (pe > pos_tol * aperture)
-    bad_dir = same & (de > dir_tol)
+    dtol = dir_tol * (np.ones(n) if dir_gain is None else np.asarray(dir_gain))
+    bad_dir = same & (de > dtol)
     dsteps = orc["steps"].astype(np.int64) - gpu["steps"].astype(np.int64)
     rep = {
         "n": n,
@@ -62,6 +129,7 @@ def compare(orc, gpu, aperture, pos_tol=1e-4, dir_tol=1e-4):
         "pos_err_p50": float(np.percentile(pe[same], 50)) if same.any() else 0.0,
         "dir_err_max": float(de[same].max()) if same.any() else 0.0,
         "dir_err_p99": float(np.percentile(de[same], 99)) if same.any() else 0.0,
+        "dir_err_inside_max": float((de / (dtol / dir_tol))[same].max()) if same.any() else 0.0,
         "exempt_pos_err_max": float(pe[ex_o].max()) if ex_o.any() else 0.0,
         "tir_total_oracle": int(orc["ntir"].sum()),
         "btir_total_oracle": int(orc["nbtir"].sum()),

@@ -584,3 +584,34 @@ def test_exit_plane_is_straight_continuation(orc):
     rc = orc.trace(med, (np.array([[0.5, 0.5, 0.5]]), np.array([[0, 0, -1.0]])),
                    P(1e-3, exit_plane_z=1.2))
     assert rc["status"][0] == orc.NO_PLANE
+
+
+def test_exit_gain_is_the_derivative_of_snells_law():
+    """The parity bar on exit directions is widened by the derivative of the
+    exit refraction; check that factor against a finite difference of the
+    scalar law n_in sin t_in = n_amb sin t_out, for a box face and a sphere."""
+    from parity import exit_gain, surface_normal
+
+    n_in, n_amb = 1.5, 1.0
+    t_in = np.array([0.1, 0.4, 0.6, 0.72])  # critical angle asin(1/1.5) = 0.7297
+    t_out = np.arcsin(n_in / n_amb * np.sin(t_in))
+    h = 1e-7
+    fd = (np.arcsin(n_in / n_amb * np.sin(t_in + h)) - np.arcsin(n_in / n_amb * np.sin(t_in - h))) / (2 * h)
+    # exits through the face z = 1 of the unit box, direction in the x-z plane
+    P = np.column_stack([np.full(4, 0.3), np.full(4, 0.6), np.ones(4)])
+    D = np.column_stack([np.sin(t_out), np.zeros(4), np.cos(t_out)])
+    spec = {"boundary": {"kind": "box", "params": np.array([0, 0, 0, 1, 1, 1.0])}, "n_amb": n_amb}
+    orc = {"status": np.zeros(4, np.uint32), "P": P, "D": D}
+    g = exit_gain(spec, orc, lambda Q: np.full(len(Q), n_in))
+    assert np.allclose(g, fd, rtol=1e-5), (g, fd)
+    # the same exits through a sphere of radius 2 about the origin
+    spec_s = {"boundary": {"kind": "sphere", "params": np.array([0, 0, 0, 2.0])}, "n_amb": n_amb}
+    N = np.array([0.0, 0.6, 0.8])
+    assert np.allclose(surface_normal(spec_s["boundary"], 2.0 * N[None, :]), N[None, :])
+    e1 = np.cross(N, [1.0, 0, 0]); e1 /= np.linalg.norm(e1)
+    Ds = np.cos(t_out)[:, None] * N[None, :] + np.sin(t_out)[:, None] * e1[None, :]
+    orc_s = {"status": np.zeros(4, np.uint32), "P": np.tile(2.0 * N, (4, 1)), "D": Ds}
+    assert np.allclose(exit_gain(spec_s, orc_s, lambda Q: np.full(len(Q), n_in)), fd, rtol=1e-5)
+    # not on the surface (an exit plane) or not exited: no widening
+    orc_p = {"status": np.array([0, 2, 0, 0], np.uint32), "P": P + [0, 0, 0.5], "D": D}
+    assert np.all(exit_gain(spec, orc_p, lambda Q: np.full(len(Q), n_in)) == 1.0)

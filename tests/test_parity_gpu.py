@@ -72,7 +72,7 @@ def test_luneburg_fp64_all_rays(vrt, ctx, orc):
     spec, rays, prm = workloads.luneburg_beam()
     o = orc.trace(spec, rays, prm)
     g = run_gpu(vrt, ctx, spec, rays, prm, "fp64")
-    report("luneburg fp64", compare(o, g, aperture=2.0))
+    report("luneburg fp64", compare(o, g, aperture=2.0, spec=spec))
     tight(o, g, tol=1e-12)
 
 
@@ -80,7 +80,7 @@ def test_luneburg_fp32c_all_rays(vrt, ctx, orc):
     spec, rays, prm = workloads.luneburg_beam()
     o = orc.trace(spec, rays, prm)
     g = run_gpu(vrt, ctx, spec, rays, prm, "fp32c")
-    rep = compare(o, g, aperture=2.0)
+    rep = compare(o, g, aperture=2.0, spec=spec)
     report("luneburg fp32c", rep)
     assert_parity(rep)
 
@@ -98,14 +98,14 @@ def gauss_case(orc):
 def test_gaussian_fp64(vrt, ctx, gauss_case):
     spec, rays, prm, o = gauss_case
     g = run_gpu(vrt, ctx, spec, rays, prm, "fp64")
-    report("gaussian fp64", compare(o, g, aperture=1.0))
+    report("gaussian fp64", compare(o, g, aperture=1.0, spec=spec))
     tight(o, g, tol=1e-8)
 
 
 def test_gaussian_fp32c(vrt, ctx, gauss_case):
     spec, rays, prm, o = gauss_case
     g = run_gpu(vrt, ctx, spec, rays, prm, "fp32c")
-    rep = compare(o, g, aperture=1.0)
+    rep = compare(o, g, aperture=1.0, spec=spec)
     report("gaussian fp32c", rep)
     assert_parity(rep)
 
@@ -133,7 +133,7 @@ def grid_case(orc):
 def test_grid_fp64_identical(vrt, ctx, grid_case):
     spec, rays, prm, o = grid_case
     g = run_gpu(vrt, ctx, spec, rays, prm, "fp64")
-    report("grid fp64", compare(o, g, aperture=1.0))
+    report("grid fp64", compare(o, g, aperture=1.0, spec=spec))
     tight(o, g, tol=1e-12)
 
 
@@ -144,7 +144,7 @@ def test_grid_fp32c_truncated_march(vrt, ctx, orc, grid_case):
     o = orc.trace(spec, rays, p128)
     g = run_gpu(vrt, ctx, spec, rays, p128, "fp32c")
     bad = ill_conditioned(orc.trace, spec, rays, p128)
-    rep = compare(exempt(o, bad), exempt(g, bad), aperture=1.0)
+    rep = compare(exempt(o, bad), exempt(g, bad), aperture=1.0, spec=spec)
     rep["ill_conditioned"] = int(bad.sum())
     report("grid fp32c first 128 moves", rep)
     assert bad.sum() <= 0.01 * len(bad)
@@ -183,7 +183,7 @@ def test_helix(vrt, ctx, orc, precision):
                 rays[1].astype(np.float32).astype(np.float64))
     o = orc.trace(spec, rays, prm)
     g = run_gpu(vrt, ctx, spec, rays, prm, precision)
-    rep = compare(o, g, aperture=10.0)
+    rep = compare(o, g, aperture=10.0, spec=spec)
     report(f"helix {precision}", rep)
     if precision == "fp64":
         tight(o, g, tol=1e-9)
@@ -218,7 +218,7 @@ def test_media_and_surfaces(vrt, ctx, orc, name, precision):
     prm = workloads.trace_params(1e-3, 50000)
     o = orc.trace(spec, (P0, d0), prm)
     g = run_gpu(vrt, ctx, spec, (P0, d0), prm, precision)
-    rep = compare(o, g, aperture=ap)
+    rep = compare(o, g, aperture=ap, spec=spec)
     report(f"{name} {precision}", rep)
     if precision == "fp64":
         tight(o, g, tol=1e-9)
@@ -270,7 +270,7 @@ def test_tangential_rule_meridional_ray(vrt, ctx, orc, precision):
     o = orc.trace(spec, (P0, d0), prm)
     g = run_gpu(vrt, ctx, spec, (P0, d0), prm, precision)
     assert np.all(o["flags"] & 2) and np.all(g["flags"] & 2)
-    rep = compare(o, g, aperture=10.0)
+    rep = compare(o, g, aperture=10.0, spec=spec)
     report(f"meridional {precision}", rep)
     assert rep["status_mismatch"] == 0 and rep["pos_fail"] == 0 and rep["dir_fail"] == 0
 
@@ -324,7 +324,7 @@ def test_full_size_sampled_parity(vrt, ctx, orc):
     idx = np.sort(np.random.default_rng(2024).choice(n, 1024, replace=False))
     o = orc.trace(spec, (P0[idx], d0[idx]), prm)
     sub = {k: v[idx] for k, v in g.items()}
-    rep = compare(o, sub, aperture=1.0)
+    rep = compare(o, sub, aperture=1.0, spec=spec)
     report("gaussian fp32c full-size sample", rep)
     assert_parity(rep)
 
