@@ -117,7 +117,7 @@ def cpu_baseline(spec, rays, prm, sample, g_res, aperture):
 
     sub = {k: v[:n] for k, v in g_res.items()}
     rep = compare(r, sub, aperture=aperture, spec=spec)
-    keys = ("n", "flagged_oracle", "flagged_gpu", "status_mismatch", "tir_mismatch",
+    keys = ("n", "flagged_oracle", "flagged_gpu", "soft_flips", "status_mismatch", "tir_mismatch",
             "btir_mismatch", "pos_fail", "dir_fail", "steps_mismatch", "pos_err_max", "pos_err_p99",
             "dir_err_max", "dir_err_p99", "dir_err_inside_max")
     return base, {k: rep[k] for k in keys}

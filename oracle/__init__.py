@@ -27,6 +27,8 @@ BOUNDARIES = {"box": 0, "sphere": 1, "cylinder": 2}
 
 EXITED, MISSED, TRUNCATED, NO_PLANE, INVALID_INPUT, REFLECTED_AT_ENTRY = range(6)
 F_NEAR_CRITICAL, F_TANGENT, F_STRAIGHT, F_BOUNDARY_TIR, F_NEAR_TIE, F_NEAR_GRAZING = 1, 2, 4, 8, 16, 32
+# the three windows ten times wider
+F_NEAR_CRITICAL_WIDE, F_NEAR_TIE_WIDE, F_NEAR_GRAZING_WIDE = 64, 128, 256
 
 
 def build(force=True):

@@ -38,6 +38,9 @@
  *     or the other); a move whose end lies within tie_eps of the enclosing
  *     surface, measured perpendicular to it, is flagged as a near tie (the
  *     choice "full step or cut at the surface" is then decided by rounding).
+ *     Each of the three windows is also checked ten times wider (flag bits
+ *     64, 128, 256): a decision that close may still go either way once the
+ *     state carries the rounding of a single-precision march.
  * The incident direction I_i is carried as the previous R (Eq. (6) gives the
  * same vector in exact arithmetic).
  */
@@ -414,6 +417,13 @@ static int near_critical(double mu, double c, double D, double eps) {
     return fabs(th_inc - th_c) < eps;
 }
 
+/* flag bits for a decision near the critical angle: the narrow window and the
+ * ten times wider one */
+static uint32_t critical_flags(double mu, double c, double D, double eps) {
+    if (!near_critical(mu, c, D, 10.0 * eps)) return 0;
+    return ORC_F_NEAR_CRITICAL_WIDE | (near_critical(mu, c, D, eps) ? ORC_F_NEAR_CRITICAL : 0);
+}
+
 /* Eq. (20): reflected unit direction I - 2 (I.N) N, normalised. */
 static void reflect(const double I[3], const double N[3], double c, double R[3]) {
     double v[3];
@@ -513,7 +523,7 @@ static void trace_one(const orc_medium *m, const orc_params *q, const double P0[
         double mu = m->n_amb / n_in;
         double c = dot3(N, I);
         double D = 1.0 - mu * mu * (1.0 - c * c);
-        if (near_critical(mu, c, D, q->crit_rad)) o->flags |= ORC_F_NEAR_CRITICAL;
+        o->flags |= critical_flags(mu, c, D, q->crit_rad);
         if (D <= 0.0) {
             o->status = ORC_REFLECTED_AT_ENTRY;
             reflect(I, N, c, R);
@@ -559,8 +569,11 @@ interior_step:
             } else {
                 double mu = n_last / ni; /* mu_i = n_{i-1} / n_i */
                 double D = 1.0 - mu * mu * (1.0 - c * c);
-                if (near_critical(mu, c, D, q->crit_rad)) o->flags |= ORC_F_NEAR_CRITICAL;
-                if (mu < 1.0 && fabs(c) < q->crit_rad) o->flags |= ORC_F_NEAR_GRAZING;
+                o->flags |= critical_flags(mu, c, D, q->crit_rad);
+                if (mu < 1.0 && fabs(c) < 10.0 * q->crit_rad) {
+                    o->flags |= ORC_F_NEAR_GRAZING_WIDE;
+                    if (fabs(c) < q->crit_rad) o->flags |= ORC_F_NEAR_GRAZING;
+                }
                 if (D <= 0.0) {
                     /* case (v): TIR, Eqs. (19)-(20) */
                     reflect(I, N, c, R);
@@ -582,7 +595,11 @@ interior_step:
                 double Pe[3], Ne[3];
                 for (int a = 0; a < 3; ++a) Pe[a] = P[a] + tx * R[a];
                 outward_normal(m, Pe, face, Ne);
-                if (fabs(tx - Delta) * fabs(dot3(R, Ne)) < q->tie_eps) o->flags |= ORC_F_NEAR_TIE;
+                double dist = fabs(tx - Delta) * fabs(dot3(R, Ne));
+                if (dist < 10.0 * q->tie_eps) {
+                    o->flags |= ORC_F_NEAR_TIE_WIDE;
+                    if (dist < q->tie_eps) o->flags |= ORC_F_NEAR_TIE;
+                }
             }
             if (tx > Delta) {
                 /* Eq. (3) */
@@ -607,7 +624,7 @@ interior_step:
             double mu = n_last / m->n_amb;
             double c = dot3(N, R);
             double D = 1.0 - mu * mu * (1.0 - c * c);
-            if (near_critical(mu, c, D, q->crit_rad)) o->flags |= ORC_F_NEAR_CRITICAL;
+            o->flags |= critical_flags(mu, c, D, q->crit_rad);
             if (D <= 0.0) {
                 double Rr[3];
                 reflect(R, N, c, Rr);

@@ -43,7 +43,9 @@ enum {
 enum {
     ORC_F_NEAR_CRITICAL = 1, ORC_F_TANGENT = 2, ORC_F_STRAIGHT = 4, ORC_F_BOUNDARY_TIR = 8,
     ORC_F_NEAR_TIE = 16,    /* a step ended within tie_eps (perpendicular) of the surface */
-    ORC_F_NEAR_GRAZING = 32 /* a refraction into higher index had |N.I| < crit_rad */
+    ORC_F_NEAR_GRAZING = 32, /* a refraction into higher index had |N.I| < crit_rad */
+    /* the same three windows ten times wider */
+    ORC_F_NEAR_CRITICAL_WIDE = 64, ORC_F_NEAR_TIE_WIDE = 128, ORC_F_NEAR_GRAZING_WIDE = 256
 };
 
 typedef struct {

@@ -545,15 +545,35 @@ def test_near_critical_flag_at_the_critical_angle(orc):
     rad of the critical angle asin(1/1.5) (Eq. (19))."""
     med = homogeneous(1.5, box((0, 0, 0), (1, 1, 1)))
     thc = math.asin(1 / 1.5)
-    cases = [(+3e-7, True, True), (-3e-7, False, True), (+1e-5, True, False),
-             (-1e-5, False, False)]
-    for dth, tir, flagged in cases:
+    # (offset, TIR, within 1e-6, within the wide window 1e-5)
+    cases = [(+3e-7, True, True, True), (-3e-7, False, True, True),
+             (+5e-6, True, False, True), (-5e-6, False, False, True),
+             (+2e-5, True, False, False), (-2e-5, False, False, False)]
+    for dth, tir, flagged, wide in cases:
         th = thc + dth
         d = np.array([[math.sin(th), 0.0, math.cos(th)]])
         P0 = np.array([[0.02, 0.5, 0.95]])
         r = orc.trace(med, (P0, d), P(1e-3))
         assert bool(r["flags"][0] & orc.F_NEAR_CRITICAL) == flagged, dth
+        assert bool(r["flags"][0] & orc.F_NEAR_CRITICAL_WIDE) == wide, dth
         assert (r["nbtir"][0] >= 1) == tir, dth
+
+
+def test_wide_flag_windows_are_the_narrow_ones_scaled(orc):
+    """Bits 64/128/256 with windows (crit_rad, tie_eps) equal bits 1/16/32 with
+    ten times those windows, on a Gaussian-bump medium with many TIRs."""
+    spec, (P0, d0), prm = workloads.gaussian_cube(n_rays=1 << 20)
+    P0, d0 = P0[:2048], d0[:2048]
+    a = orc.trace(spec, (P0, d0), prm)
+    wide = dict(prm, crit_rad=10 * prm["crit_rad"], tie_eps=10 * prm["tie_eps"])
+    b = orc.trace(spec, (P0, d0), wide)
+    for narrow_bit, wide_bit in ((orc.F_NEAR_CRITICAL, orc.F_NEAR_CRITICAL_WIDE),
+                                 (orc.F_NEAR_TIE, orc.F_NEAR_TIE_WIDE),
+                                 (orc.F_NEAR_GRAZING, orc.F_NEAR_GRAZING_WIDE)):
+        assert np.array_equal((a["flags"] & wide_bit) != 0, (b["flags"] & narrow_bit) != 0)
+        # the narrow window lies inside the wide one
+        assert not np.any((a["flags"] & narrow_bit) & ~((a["flags"] & wide_bit) // wide_bit * narrow_bit))
+        assert ((b["flags"] & narrow_bit) != 0).sum() > 0
 
 
 def test_statuses(orc):
