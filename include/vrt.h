@@ -96,7 +96,10 @@ typedef struct {
     double exit_plane_z;  /* NaN: no exit plane; otherwise exiting rays are continued
                              straight to z = exit_plane_z (status NO_PLANE if they cannot) */
     int32_t precision;    /* vrt_precision */
-    int32_t reserved;     /* must be 0 */
+    int32_t max_lanes;    /* VRT_FP32_COMP: at most this many persistent lanes (rounded up to a
+                             multiple of 256) pull rays from the batch's queue; 0 = as many as
+                             the device keeps resident.  A ray's result does not depend on it.
+                             Must be 0 for VRT_FP64 (one lane per ray). */
 } vrt_trace_params;
 
 /* Ray batch, structure of arrays, all device pointers.  Element type is

@@ -47,7 +47,7 @@ class vrt_boundary(C.Structure):
 class vrt_trace_params(C.Structure):
     _fields_ = [("dL0", C.c_double), ("max_steps", C.c_int64), ("eps_tan", C.c_double),
                 ("crit_rad", C.c_double), ("tie_eps", C.c_double), ("exit_plane_z", C.c_double),
-                ("precision", C.c_int32), ("reserved", C.c_int32)]
+                ("precision", C.c_int32), ("max_lanes", C.c_int32)]
 
 
 class vrt_rays(C.Structure):
@@ -230,7 +230,7 @@ def make_params(p, precision):
     z = p.get("exit_plane_z")
     q.exit_plane_z = math.nan if z is None else float(z)
     q.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    q.reserved = 0
+    q.max_lanes = int(p.get("max_lanes", 0))
     return q
 
 

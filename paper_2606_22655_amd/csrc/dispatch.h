@@ -17,6 +17,7 @@ struct LaunchArgs {
     uint32_t *queue;  // FP32_COMP: ray-queue counter (device), zeroed by the launcher
     int num_cu;
     int blocks_per_cu;  // FP32_COMP persistent grid: blocks of 256 lanes per CU (0 = default)
+    uint32_t max_blocks;  // FP32_COMP persistent grid: cap on the blocks (0 = none)
 };
 
 hipError_t launch_march_fp64(const LaunchArgs &a);

@@ -21,7 +21,11 @@
 //     refraction/TIR decision can be taken or where gamma is sensitive to the
 //     normal -- the normal, c, D and the new direction are recomputed in
 //     double from the compensated position (every TIR goes through here);
-//   - launch, entry, surface events and the exit plane run in double.
+//   - launch, entry, surface events and the exit plane run in double;
+//   - |I| is not renormalized: the Snell increment keeps |R| = |I| in exact
+//     arithmetic and its rounding adds ~1e-11 per step to the compensated sum,
+//     so a ray's result depends only on its own steps, never on the lane or
+//     the moment that runs it.
 //
 // Scheduling: the grid is sized to the machine, not to the batch.  When a
 // lane's ray ends, the wave counts its idle lanes with a ballot, one lane
@@ -110,7 +114,8 @@ __device__ __forceinline__ void grid_locate(const MediumDev &m, float phx, float
     fz = w - (double)ck;
 }
 
-__device__ __forceinline__ void grid_fetch(const MediumDev &m, GridCache &gc, int ci, int cj, int ck) {
+__device__ __forceinline__ void grid_fetch(const MediumDev &m, const float4 *__restrict__ rec, GridCache &gc, int ci, int cj,
+                                           int ck) {
     gc.ci = ci;
     gc.cj = cj;
     gc.ck = ck;
@@ -118,21 +123,21 @@ __device__ __forceinline__ void grid_fetch(const MediumDev &m, GridCache &gc, in
     const size_t o = (size_t)ck * sz + (size_t)cj * sy + ci;
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-        gc.v[j] = m.rec[o + (j & 1) * sx + ((j >> 1) & 1) * sy + ((j >> 2) & 1) * sz];
+        gc.v[j] = rec[o + (j & 1) * sx + ((j >> 1) & 1) * sy + ((j >> 2) & 1) * sz];
 }
 
 // n, grad n and n(P_i) - n(P_{i-1}) for the discretized medium.  The index
 // is kept as cell base value + offset (nb, nd): the base is a node value and
 // the offset is accurate to double rounding, so the difference to the
 // previous point's (nlb, nld) keeps full precision within and across cells.
-__device__ __forceinline__ void grid32(const MediumDev &m, GridCache &gc, float px, float py, float pz,
+__device__ __forceinline__ void grid32(const MediumDev &m, const float4 *__restrict__ rec, GridCache &gc, float px, float py, float pz,
                                        float pcx, float pcy, float pcz, float nlb, double nld,
                                        float &n, float &nb, double &nd, float &gx, float &gy,
                                        float &gz, float &dn) {
     int ci, cj, ck;
     double fx, fy, fz;
     grid_locate(m, px, py, pz, pcx, pcy, pcz, ci, cj, ck, fx, fy, fz);
-    if (ci != gc.ci || cj != gc.cj || ck != gc.ck) grid_fetch(m, gc, ci, cj, ck);
+    if (ci != gc.ci || cj != gc.cj || ck != gc.ck) grid_fetch(m, rec, gc, ci, cj, ck);
     double delta;
     grid_blend(gc, fx, fy, fz, delta, gx, gy, gz);
     gx *= m.finv_h[0];  // records hold node differences per node spacing
@@ -146,7 +151,8 @@ __device__ __forceinline__ void grid32(const MediumDev &m, GridCache &gc, float 
 
 // n and grad n in double at P from the cell records (exact node differences
 // per spacing): the cached cell when P lies in it, else the cell is loaded.
-__device__ inline void grid_eval64(const MediumDev &m, const GridCache &gc, d3 P, double &n, d3 &g) {
+__device__ inline void grid_eval64(const MediumDev &m, const float4 *__restrict__ rec, const GridCache &gc, d3 P, double &n,
+                                   d3 &g) {
     const int nn[3] = {m.nx, m.ny, m.nz};
     int c[3];
     double f[3];
@@ -166,7 +172,7 @@ __device__ inline void grid_eval64(const MediumDev &m, const GridCache &gc, d3 P
     g = mk(0, 0, 0);
     for (int j = 0; j < 8; ++j) {
         const float4 r = cached ? gc.v[j]
-                                : m.rec[o + (j & 1) + ((j >> 1) & 1) * sy + ((j >> 2) & 1) * sz];
+                                : rec[o + (j & 1) + ((j >> 1) & 1) * sy + ((j >> 2) & 1) * sz];
         const double w = ((j & 1) ? f[0] : 1.0 - f[0]) * ((j & 2) ? f[1] : 1.0 - f[1]) *
                          ((j & 4) ? f[2] : 1.0 - f[2]);
         n += w * (double)r.x;
@@ -196,7 +202,8 @@ __device__ __forceinline__ void write_out(const RaysDev<float> &io, const Lane &
 
 // Index at a surface point in the representation the march keeps.
 template <int MK>
-__device__ __forceinline__ void index_at_event(const MediumDev &m, GridCache &gc, d3 P, float &nlb,
+__device__ __forceinline__ void index_at_event(const MediumDev &m, const float4 *__restrict__ rec, GridCache &gc, d3 P,
+                                               float &nlb,
                                                double &nld) {
     if constexpr (MK == VRT_MEDIUM_GRID) {
         float n, gx, gy, gz, dn;
@@ -205,7 +212,7 @@ __device__ __forceinline__ void index_at_event(const MediumDev &m, GridCache &gc
         split(P.x, phx, pcx);
         split(P.y, phy, pcy);
         split(P.z, phz, pcz);
-        grid32(m, gc, phx, phy, phz, pcx, pcy, pcz, 0.f, 0.0, n, nlb, nld, gx, gy, gz, dn);
+        grid32(m, rec, gc, phx, phy, phz, pcx, pcy, pcz, 0.f, 0.0, n, nlb, nld, gx, gy, gz, dn);
     } else {
         nlb = (float)index64<MK>(m, P);
         nld = 0.0;
@@ -215,7 +222,7 @@ __device__ __forceinline__ void index_at_event(const MediumDev &m, GridCache &gc
 // Start ray L.r: launch state, straight flight in the surroundings and entry
 // refraction (double).  Returns false if the ray already ended (written).
 template <int MK>
-__device__ bool lane_init(const MediumDev &m, const BoundaryDev &b, const TraceDev &t,
+__device__ bool lane_init(const MediumDev &m, const float4 *__restrict__ rec, const BoundaryDev &b, const TraceDev &t,
                           const RaysDev<float> &io, Lane &L, GridCache &gc) {
     const uint32_t r = L.r;
     L.steps = L.ntir = L.nbtir = L.flags = 0;
@@ -235,7 +242,7 @@ __device__ bool lane_init(const MediumDev &m, const BoundaryDev &b, const TraceD
         split(I.x, L.Ihx, L.Icx);
         split(I.y, L.Ihy, L.Icy);
         split(I.z, L.Ihz, L.Icz);
-        index_at_event<MK>(m, gc, P0, L.nlb, L.nld);
+        index_at_event<MK>(m, rec, gc, P0, L.nlb, L.nld);
         L.pending = false;
         return true;
     }
@@ -263,27 +270,17 @@ __device__ bool lane_init(const MediumDev &m, const BoundaryDev &b, const TraceD
     split(R.x, L.Ihx, L.Icx);
     split(R.y, L.Ihy, L.Icy);
     split(R.z, L.Ihz, L.Icz);
-    index_at_event<MK>(m, gc, P, L.nlb, L.nld);
+    index_at_event<MK>(m, rec, gc, P, L.nlb, L.nld);
     L.Delta = (float)(t.dL0 / n_in);
     L.pending = true;
     return true;
 }
 
-// Restore |I| = 1 against the drift of rounding in the increments.  Called
-// for the whole wave at once (every 64 iterations), so the double-precision
-// work is not repeated for each lane's own schedule.
-__device__ __forceinline__ void lane_renorm(Lane &L) {
-    d3 I = mk((double)L.Ihx - L.Icx, (double)L.Ihy - L.Icy, (double)L.Ihz - L.Icz);
-    I = (1.0 / sqrt(dot(I, I))) * I;
-    split(I.x, L.Ihx, L.Icx);
-    split(I.y, L.Ihy, L.Icy);
-    split(I.z, L.Ihz, L.Icz);
-}
-
 // One decision (unless pending) and one move.  Returns false when the ray
 // ended (written).
 template <int MK>
-__device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, const BoundaryDev &b,
+__device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, const float *__restrict__ bumps,
+                                          const float4 *__restrict__ rec, const BoundaryDev &b,
                                           const TraceDev &t, const RaysDev<float> &io, Lane &L,
                                           GridCache &gc, float dL0, float eps_tan, float mrg) {
     if (!L.pending) {
@@ -291,11 +288,12 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
         double nd = 0.0;
         const float n_last = (float)((double)L.nlb + L.nld);
         if constexpr (MK == VRT_MEDIUM_GRID) {
-            grid32(m, gc, L.Phx, L.Phy, L.Phz, L.Pcx, L.Pcy, L.Pcz, L.nlb, L.nld, ni, nb, nd, gx,
+            grid32(m, rec, gc, L.Phx, L.Phy, L.Phz, L.Pcx, L.Pcy, L.Pcz, L.nlb, L.nld, ni, nb, nd, gx,
                    gy, gz, dn);
         } else {
             f3 g;
-            med32<MK>(m, mf, mkf(L.Phx, L.Phy, L.Phz), mkf(L.sx, L.sy, L.sz), n_last, ni, g, dn);
+            med32<MK>(m, mf, bumps, mkf(L.Phx, L.Phy, L.Phz), mkf(L.sx, L.sy, L.sz), n_last, ni, g,
+                      dn);
             gx = g.x;
             gy = g.y;
             gz = g.z;
@@ -321,11 +319,11 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
                     float pb, px, py, pz;
                     double pd;
                     GridCache g2 = gc;
-                    grid32(m, g2, L.Phx + qx, L.Phy + qy, L.Phz + qz, L.Pcx, L.Pcy, L.Pcz, nb, nd, np,
+                    grid32(m, rec, g2, L.Phx + qx, L.Phy + qy, L.Phz + qz, L.Pcx, L.Pcy, L.Pcz, nb, nd, np,
                            pb, pd, px, py, pz, dnp);
                 } else {
                     f3 gp;
-                    med32<MK>(m, mf, mkf(L.Phx + qx, L.Phy + qy, L.Phz + qz), mkf(qx, qy, qz), ni,
+                    med32<MK>(m, mf, bumps, mkf(L.Phx + qx, L.Phy + qy, L.Phz + qz), mkf(qx, qy, qz), ni,
                               np, gp, dnp);
                 }
                 const float a = dnp * frcp(2.0f * ni);
@@ -348,8 +346,8 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
                     d3 g64, gp;
                     double ni64, np64;
                     if constexpr (MK == VRT_MEDIUM_GRID) {
-                        grid_eval64(m, gc, P64, ni64, g64);
-                        grid_eval64(m, gc, Pp64, np64, gp);
+                        grid_eval64(m, rec, gc, P64, ni64, g64);
+                        grid_eval64(m, rec, gc, Pp64, np64, gp);
                     } else {
                         med64<MK>(m, P64, ni64, g64);
                         med64<MK>(m, Pp64, np64, gp);
@@ -450,7 +448,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
         split(R.y, L.Ihy, L.Icy);
         split(R.z, L.Ihz, L.Icz);
         L.Delta = (float)(t.dL0 / n_last);
-        index_at_event<MK>(m, gc, P, L.nlb, L.nld);
+        index_at_event<MK>(m, rec, gc, P, L.nlb, L.nld);
         L.nbtir++;
         L.flags |= VRT_FLAG_BOUNDARY_TIR;
         L.pending = true;
@@ -487,8 +485,9 @@ struct Launch32 {
 };
 
 template <int MK>
-__global__ __launch_bounds__(256) void march_fp32c_kernel(Launch32 desc, uint32_t n,
-                                                          uint32_t *queue) {
+__global__ __launch_bounds__(256, MK == VRT_MEDIUM_GRID ? 2 : 3) void march_fp32c_kernel(
+    Launch32 desc, const float *__restrict__ bumps, const float4 *__restrict__ rec, uint32_t n,
+    uint32_t *queue) {
     const Launch32 *__restrict__ D = &desc;
     const MediumDev &m = D->m;
     const MedF &mf = D->mf;
@@ -504,7 +503,6 @@ __global__ __launch_bounds__(256) void march_fp32c_kernel(Launch32 desc, uint32_
     // a step whose end is this far inside cannot be within tie_eps of a cut
     const float mrg = fmaxf(2e-6f, 4.0f * (float)t.tie_eps);
     const int lane = __lane_id();
-    uint32_t it = 0;  // iterations of the wave (uniform)
     for (;;) {
         const bool need = !active && !done;
         const uint64_t nm = __ballot(need);
@@ -519,16 +517,12 @@ __global__ __launch_bounds__(256) void march_fp32c_kernel(Launch32 desc, uint32_
                     done = true;
                 } else {
                     L.r = r;
-                    active = lane_init<MK>(m, b, t, io, L, gc);
+                    active = lane_init<MK>(m, rec, b, t, io, L, gc);
                 }
             }
         }
-        if (!__ballot(active)) {
-            if (!__ballot(!done)) break;
-            continue;
-        }
-        if (active) active = lane_step<MK>(m, mf, b, t, io, L, gc, dL0, eps_tan, mrg);
-        if ((++it & 63u) == 0u && active) lane_renorm(L);
+        if (!__ballot(active) && !__ballot(!done)) break;
+        if (active) active = lane_step<MK>(m, mf, bumps, rec, b, t, io, L, gc, dL0, eps_tan, mrg);
     }
 }
 
@@ -549,10 +543,11 @@ static hipError_t launch32(const LaunchArgs &a) {
     uint32_t blocks = (uint32_t)(a.num_cu > 0 ? a.num_cu : 256) * (uint32_t)per_cu;
     const uint32_t need = (a.n + 255u) / 256u;
     if (blocks > need) blocks = need;
+    if (a.max_blocks > 0 && blocks > a.max_blocks) blocks = a.max_blocks;
     hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, a.stream, a.queue);
     const Launch32 desc{a.m, a.mf, a.b, a.t, a.io32};
-    hipLaunchKernelGGL(march_fp32c_kernel<MK>, dim3(blocks), dim3(256), 0, a.stream, desc, a.n,
-                       a.queue);
+    hipLaunchKernelGGL(march_fp32c_kernel<MK>, dim3(blocks), dim3(256), 0, a.stream, desc,
+                       a.m.bumps_f, a.m.rec, a.n, a.queue);
     return hipGetLastError();
 }
 

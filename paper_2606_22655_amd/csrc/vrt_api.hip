@@ -462,7 +462,8 @@ int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, s
     if (!(p->dL0 > 0.0) || !isfinite(p->dL0)) return fail(VRT_EINVAL, "vrt_trace: dL0 must be > 0");
     if (p->max_steps <= 0 || p->max_steps > 0xFFFFFFFFll)
         return fail(VRT_EINVAL, "vrt_trace: max_steps must be in [1, 2^32)");
-    if (p->reserved != 0) return fail(VRT_EINVAL, "vrt_trace: reserved must be 0");
+    if (p->max_lanes < 0 || (p->precision == VRT_FP64 && p->max_lanes != 0))
+        return fail(VRT_EINVAL, "vrt_trace: max_lanes must be >= 0 (and 0 for VRT_FP64)");
     if (!(p->eps_tan >= 0.0) || !(p->crit_rad >= 0.0) || !(p->tie_eps >= 0.0) ||
         !(p->tie_eps <= 1e-6))
         return fail(VRT_EINVAL, "vrt_trace: eps_tan, crit_rad >= 0 and tie_eps in [0, 1e-6]");
@@ -496,6 +497,7 @@ int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, s
     a.stream = (hipStream_t)stream;
     a.num_cu = ctx->num_cu;
     a.blocks_per_cu = 0;
+    a.max_blocks = p->max_lanes > 0 ? (uint32_t)((p->max_lanes + 255) / 256) : 0u;
     hipError_t e;
     if (p->precision == VRT_FP64) {
         a.io64 = RaysDev<double>{(const double *)rays->px, (const double *)rays->py,

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import workloads
-from parity import (assert_parity, assert_stats, compare, exempt, ill_conditioned,
+from parity import (WIDE, assert_parity, assert_stats, compare, exempt, ill_conditioned,
                     stat_compare)
 
 pytestmark = pytest.mark.gpu
@@ -59,6 +59,7 @@ def report(name, rep):
 
 
 def tight(orc, gpu, tol=1e-9):
+    orc = dict(orc, flags=orc["flags"] & np.uint32(0xFFFFFFFF ^ WIDE))  # wide windows: oracle only
     for k in ("status", "steps", "ntir", "nbtir", "flags"):
         assert np.array_equal(orc[k], gpu[k]), (k, np.nonzero(orc[k] != gpu[k])[0][:10])
     assert np.abs(orc["P"] - gpu["P"]).max() < tol
@@ -296,17 +297,22 @@ def test_counters_match_outputs(vrt, ctx):
 
 
 def test_alone_equals_in_batch_bitwise(vrt, ctx):
-    """A ray's result does not depend on which lane, wave or batch runs it."""
+    """A ray's result does not depend on which lane, wave or batch runs it, nor
+    on when its lane picks it from the queue: the batch runs on one block of
+    256 lanes (max_lanes) so that every lane marches about 12 rays in turn, and
+    on 8 blocks with the rays shuffled; both equal the rays run alone."""
     spec, (P0, d0), prm = workloads.gaussian_cube(n_rays=3000)
-    full = run_gpu(vrt, ctx, spec, (P0, d0), prm, "fp32c")
+    full = run_gpu(vrt, ctx, spec, (P0, d0), dict(prm, max_lanes=256), "fp32c")
     idx = np.array([0, 17, 1234, 2999])
     alone = run_gpu(vrt, ctx, spec, (P0[idx], d0[idx]), prm, "fp32c")
     perm = np.random.default_rng(1).permutation(3000)
-    shuf = run_gpu(vrt, ctx, spec, (P0[perm], d0[perm]), prm, "fp32c")
+    shuf = run_gpu(vrt, ctx, spec, (P0[perm], d0[perm]), dict(prm, max_lanes=2048), "fp32c")
+    wide = run_gpu(vrt, ctx, spec, (P0, d0), prm, "fp32c")
     inv = np.argsort(perm)
     for k in ("P", "D", "status", "steps", "ntir", "nbtir", "flags"):
         assert np.array_equal(full[k][idx], alone[k]), k
         assert np.array_equal(full[k], shuf[k][inv]), k
+        assert np.array_equal(full[k], wide[k]), k
 
 
 def test_full_size_sampled_parity(vrt, ctx, orc):
@@ -347,6 +353,11 @@ def test_api_errors(vrt, ctx):
         bad["max_steps"] = 0
         with pytest.raises(vrt.VrtError):
             vrt.trace(med, b, bad, "fp32c")
+        with pytest.raises(vrt.VrtError):  # negative lane cap
+            vrt.trace(med, b, dict(prm, max_lanes=-1), "fp32c")
+        with pytest.raises(vrt.VrtError) as e:  # the FP64 march has one lane per ray
+            vrt.trace(med, vrt.RayBatch(P0, d0, "fp64"), dict(prm, max_lanes=256), "fp64")
+        assert "max_lanes" in vrt.vrt_last_error()
         # misaligned pointer
         saved = b.rays.px
         b.rays.px = saved + 2
