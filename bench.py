@@ -32,11 +32,43 @@ import workloads
 
 METRIC = "ray-steps/s at oracle-matched accuracy; served p50/p99 latency vs plain FP64 march"
 
-# MI355X peaks (256 CUs, 4 SIMD x 16 lanes each, 2.4 GHz)
-VALU_LANES_PER_S = 256 * 4 * 16 * 2.4e9  # 3.93e13 lane-instructions / s
-PEAK_FP32_NONPACKED_TFLOPS = 2 * VALU_LANES_PER_S / 1e12  # FMA = 2 flops: 78.6
-PEAK_FP32_PACKED_TFLOPS = 157.3  # published, needs packed FP32 (not used here)
+# MI355X peaks: published FP32 vector rate (256 CUs x 2.4 GHz x 256 flop/clk)
+# and HBM3E bandwidth.  The march issues more VALU lane-instructions per second
+# than 256 x 4 SIMD x 16 lanes x 2.4 GHz (3.93e13/s, measured with
+# SQ_INSTS_VALU), so that lower "non-packed" figure is not a ceiling here and
+# the published FP32 vector peak is the denominator.
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per launch of the march kernel from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch), scaled by what the same counters read for a
+# plain 2 GiB device copy (FETCH_SIZE reads half the copied bytes: x2;
+# WRITE_SIZE reads them exactly: x1).  Valid only for the kernel sources they
+# were taken on (sha256 of the files below); reported as null otherwise.
+KERNEL_SOURCES = ("march_fp32c.hip", "media.h", "vrt_common.h", "dispatch.h")
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+TRAFFIC_KIB = {  # workload -> (fetch KiB, write KiB, kernel sha256); profiles/march_fp32c_hbm_traffic.md
+    "freeform": (79749.3, 299428.1, "3907978953d2f3f7cccf527d3f8654bea236d0ad5dfc45efd2213bbb9284653b"),
+    "grid": (409733720.5, 1584197.1, "3907978953d2f3f7cccf527d3f8654bea236d0ad5dfc45efd2213bbb9284653b"),
+}
+
+
+def kernel_sha():
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2606_22655_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(workload):
+    t = TRAFFIC_KIB.get(workload)
+    if t is None or t[2] != kernel_sha():
+        return None
+    return int((t[0] * FETCH_SCALE + t[1] * WRITE_SCALE) * 1024)
 
 
 def algo_flops_per_step(workload, K=16):
@@ -116,6 +148,14 @@ def cpu_baseline(spec, rays, prm, sample, g_res, aperture):
     from parity import compare
 
     sub = {k: v[:n] for k, v in g_res.items()}
+    if spec["kind"] == "grid":
+        # single rays through the quantized grid are chaotic (the oracle's own
+        # exits move under 1e-11 launch shifts): compare distributions
+        from parity import stat_compare
+
+        rep = stat_compare(r, sub)
+        rep["kind"] = "two-sample statistics (chaotic medium)"
+        return base, rep
     rep = compare(r, sub, aperture=aperture, spec=spec)
     keys = ("n", "flagged_oracle", "flagged_gpu", "soft_flips", "status_mismatch", "tir_mismatch",
             "btir_mismatch", "pos_fail", "dir_fail", "steps_mismatch", "pos_err_max", "pos_err_p99",
@@ -174,10 +214,9 @@ def main(argv=None):
 
     flops = algo_flops_per_step(args.workload) * ray_steps
     achieved = flops / (ms / 1e3) / 1e12
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_NONPACKED_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
-            "traffic": None,
-            "frac_vs_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": traffic_bytes(args.workload) if precision == "fp32c" else None,
             "algo_flops_per_ray_step": algo_flops_per_step(args.workload),
             "kernel": "march_fp32c_kernel" if precision == "fp32c" else "march_fp64_kernel"}
     if args.workload == "grid":
