@@ -282,18 +282,20 @@ template <int MK>
 __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, const float *__restrict__ bumps,
                                           const float4 *__restrict__ rec, const BoundaryDev &b,
                                           const TraceDev &t, const RaysDev<float> &io, Lane &L,
-                                          GridCache &gc, float dL0, float eps_tan, float mrg) {
+                                          GridCache &gc, float dL0, float eps_tan, float mrg,
+                                          float crit_f) {
     if (!L.pending) {
         float ni, gx, gy, gz, dn, nb = 0.f;
         double nd = 0.0;
-        const float n_last = (float)((double)L.nlb + L.nld);
+        float n_last = L.nlb;  // analytic media keep nld = 0
+        if constexpr (MK == VRT_MEDIUM_GRID) n_last = (float)((double)L.nlb + L.nld);
         if constexpr (MK == VRT_MEDIUM_GRID) {
             grid32(m, rec, gc, L.Phx, L.Phy, L.Phz, L.Pcx, L.Pcy, L.Pcz, L.nlb, L.nld, ni, nb, nd, gx,
                    gy, gz, dn);
         } else {
             f3 g;
-            med32<MK>(m, mf, bumps, mkf(L.Phx, L.Phy, L.Phz), mkf(L.sx, L.sy, L.sz), n_last, ni, g,
-                      dn);
+            med32<MK>(m, mf, bumps, dL0, mkf(L.Phx, L.Phy, L.Phz), mkf(L.sx, L.sy, L.sz), n_last,
+                      ni, g, dn);
             gx = g.x;
             gy = g.y;
             gz = g.z;
@@ -323,7 +325,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
                            pb, pd, px, py, pz, dnp);
                 } else {
                     f3 gp;
-                    med32<MK>(m, mf, bumps, mkf(L.Phx + qx, L.Phy + qy, L.Phz + qz), mkf(qx, qy, qz), ni,
+                    med32<MK>(m, mf, bumps, dL0, mkf(L.Phx + qx, L.Phy + qy, L.Phz + qz), mkf(qx, qy, qz), ni,
                               np, gp, dnp);
                 }
                 const float a = dnp * frcp(2.0f * ni);
@@ -371,15 +373,20 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
                     split(R.x, L.Ihx, L.Icx);
                     split(R.y, L.Ihy, L.Icy);
                     split(R.z, L.Ihz, L.Icz);
-                } else {  // Eqs. (9)-(10) as an increment; D > 0 here
-                    const double mu = 1.0 + (double)m1;
-                    const double cd = (double)c;
-                    const double D = mu * mu * cd * cd - (double)m1 * (2.0 + (double)m1);
-                    if (m1 > 0.0f && fabs(D) < 2.0 * mu * mu * t.crit_rad &&
-                        near_critical(mu, cd, D, t.crit_rad))
-                        L.flags |= VRT_FLAG_NEAR_CRITICAL;
-                    const float sD = fsqrt((float)D);
-                    const float q = m1 * (2.0f + m1) * frcp(sD + (1.0f + m1) * fabsf(c));
+                } else {  // Eqs. (9)-(10) as an increment
+                    // D = mu^2 c^2 - (mu^2 - 1) >= (3/4) mu^2 c^2 here: no cancellation,
+                    // float keeps it to a few ulp.  The near-critical window needs
+                    // |D| < 2 mu^2 crit_rad (the bound in near_critical); screen for
+                    // it with 1 % slack and decide it in double.
+                    const float muf = 1.0f + m1;
+                    const float D = muf * muf * c * c - m1 * (2.0f + m1);
+                    if (m1 > 0.0f && D < 2.02f * muf * muf * crit_f) {
+                        const double mu = 1.0 + (double)m1, cd = (double)c;
+                        const double Dd = mu * mu * cd * cd - (double)m1 * (2.0 + (double)m1);
+                        if (near_critical(mu, cd, Dd, t.crit_rad)) L.flags |= VRT_FLAG_NEAR_CRITICAL;
+                    }
+                    const float sD = fsqrt(D);
+                    const float q = m1 * (2.0f + m1) * frcp(sD + muf * fabsf(c));
                     const float gam = c > 0.0f ? -q : q;  // -sgn(c) q, q signed
                     incx = m1 * L.Ihx + gam * Nx;
                     incy = m1 * L.Ihy + gam * Ny;
@@ -389,7 +396,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, co
             }
         }
         L.nlb = nb;
-        L.nld = nd;
+        if constexpr (MK == VRT_MEDIUM_GRID) L.nld = nd;
         kahan_add(L.Ihx, L.Icx, incx);
         kahan_add(L.Ihy, L.Icy, incy);
         kahan_add(L.Ihz, L.Icz, incz);
@@ -500,13 +507,18 @@ __global__ __launch_bounds__(256, MK == VRT_MEDIUM_GRID ? 2 : 3) void march_fp32
     bool active = false, done = false;
     const float dL0 = (float)t.dL0;
     const float eps_tan = (float)t.eps_tan;
+    const float crit_f = (float)t.crit_rad;
     // a step whose end is this far inside cannot be within tie_eps of a cut
     const float mrg = fmaxf(2e-6f, 4.0f * (float)t.tie_eps);
     const int lane = __lane_id();
+    // wave masks (uniform): lanes with a ray, lanes that found the queue empty.
+    // Waves are always full (256-lane blocks), so a lane needs a ray iff its
+    // bit is in neither mask.
+    uint64_t act = 0, done_m = 0;
     for (;;) {
-        const bool need = !active && !done;
-        const uint64_t nm = __ballot(need);
+        const uint64_t nm = ~(act | done_m);
         if (nm) {  // refill idle lanes from the queue with one atomic per wave
+            const bool need = !active && !done;
             const int leader = __ffsll((unsigned long long)nm) - 1;
             uint32_t base = 0;
             if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(nm));
@@ -520,9 +532,13 @@ __global__ __launch_bounds__(256, MK == VRT_MEDIUM_GRID ? 2 : 3) void march_fp32
                     active = lane_init<MK>(m, rec, b, t, io, L, gc);
                 }
             }
+            done_m = __ballot(done);
+            act = __ballot(active);
         }
-        if (!__ballot(active) && !__ballot(!done)) break;
-        if (active) active = lane_step<MK>(m, mf, bumps, rec, b, t, io, L, gc, dL0, eps_tan, mrg);
+        if (!act && done_m == ~0ull) break;
+        if (active) active = lane_step<MK>(m, mf, bumps, rec, b, t, io, L, gc, dL0, eps_tan, mrg,
+                                           crit_f);
+        act = __ballot(active);
     }
 }
 

@@ -26,6 +26,8 @@
 // the first/last node): exact in float for nearby values; grad n = h * inv_h.
 #pragma once
 
+#include <type_traits>
+
 #include "vrt_common.h"
 
 namespace vrt {
@@ -151,17 +153,18 @@ struct MedF {  // single-precision constants of the analytic media
     float q[8];
 };
 
-// expm1 by its degree-3 Taylor polynomial.  The argument is the change of a
-// bump exponent over one step, dq = ((P - c).s - |s|^2/2) / sigma^2, so with
-// t = |P - c| / sigma, |dq| <= t Delta / sigma (+ a second-order term), and
-// the dropped x^4/24 costs at most |A| exp(-t^2/2) (t Delta/sigma)^4 / 24 in
-// n_i - n_{i-1}.  Over t that peaks at t = 2 (4 e^-2 = 2.17): with
-// Delta/sigma <= 7.2e-3 (Delta <= 5e-4 / 1.4, sigma >= 0.05) and |A| <= 0.1
-// the error is below 2.5e-11 per bump, four orders under the step's own index
-// difference.
-__device__ __forceinline__ float expm1_small(float x) {
-    return x * (1.0f + x * (0.5f + x * (1.0f / 6.0f)));
-}
+// Accuracy of the truncated expm1 in the Gaussian index difference.  The
+// argument is the change of a bump exponent over one step,
+// dq = ((P - c).s - |s|^2/2) / sigma^2; with t = |P - c| / sigma and
+// rho = Delta / sigma, |dq| <= t rho (+ rho^2 / 2).  Dropping the terms from
+// x^(d+1) on costs at most |A| exp(-t^2/2) (t rho)^(d+1) / (d+1)! in
+// n_i - n_{i-1}, largest at t = sqrt(d+1).  Degree 3 is used while
+// rho <= kGaussRho3 (error < 3e-11 |A| per bump at rho = 8e-3), degree 5 up
+// to kGaussRhoMax (error < 2e-11 |A| at rho = 0.05); longer steps are refused
+// for the single-precision path.  rho is bounded per trace by
+// dL0 / (n_min sigma_min), n_min = n0 - sum |A|.
+constexpr double kGaussRho3 = 8e-3;
+constexpr double kGaussRhoMax = 5e-2;
 
 // Single-precision reciprocal and square root from the hardware
 // approximations (~1 ulp); the march needs no correctly rounded results in
@@ -173,11 +176,12 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 // table (m.bumps_f), passed from a restrict kernel argument so that its loads
 // are known not to be clobbered by the kernel's stores (scalar loads).
 // MedF.q: LINEAR [n0, gx, gy, gz]; LUNEBURG [., cx, cy, cz, 1/R^2];
-// FIBER [n_c, Delta, ., cx, cy, 2 Delta n_c^2/R^2, n_clad, R^2]; others [n0]
+// FIBER [n_c, Delta, ., cx, cy, 2 Delta n_c^2/R^2, n_clad, R^2];
+// GAUSSIAN [n0, largest dL0 for the degree-3 difference form]; others [n0]
 template <int MK>
 __device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf,
-                                      const float *__restrict__ bumps, f3 P, f3 s, float n_last,
-                                      float &n, f3 &g, float &dn) {
+                                      const float *__restrict__ bumps, float dL0, f3 P, f3 s,
+                                      float n_last, float &n, f3 &g, float &dn) {
     if constexpr (MK == VRT_MEDIUM_HOMOGENEOUS) {
         n = mf.q[0];
         g = mkf(0, 0, 0);
@@ -218,27 +222,38 @@ __device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf,
         }
     } else if constexpr (MK == VRT_MEDIUM_GAUSSIAN) {
         // E_k(P_{i-1}) = E_k(P_i) exp(dq_k), dq_k = ((P_i - c_k).s - |s|^2/2) / sigma^2,
-        // so n_i - n_{i-1} = -sum A_k E_k(P_i) expm1(dq_k).
+        // so n_i - n_{i-1} = -sum A_k E_k(P_i) expm1(dq_k), with A_k expm1 as a
+        // polynomial in y = sigma^2 dq_k whose coefficients carry A_k.
         float nn = mf.q[0], gx = 0.f, gy = 0.f, gz = 0.f, acc = 0.f;
         const float hs2 = -0.5f * dotf(s, s);
         const float *__restrict__ b = bumps;
         const int K = m.K;
+        auto bump_loop = [&](auto deg) {
 #pragma unroll 4
-        for (int k = 0; k < K; ++k) {
-            const float A = b[kBumpF * k + 0], e2 = b[kBumpF * k + 1];
-            const float cx = b[kBumpF * k + 2], cy = b[kBumpF * k + 3], cz = b[kBumpF * k + 4];
-            const float is2 = b[kBumpF * k + 5];
-            const float ox = P.x - cx, oy = P.y - cy, oz = P.z - cz;
-            const float r2 = ox * ox + oy * oy + oz * oz;
-            const float e = A * __builtin_amdgcn_exp2f(r2 * e2);
-            nn += e;
-            const float w = e * is2;
-            gx -= w * ox;
-            gy -= w * oy;
-            gz -= w * oz;
-            const float dq = (ox * s.x + oy * s.y + oz * s.z + hs2) * is2;
-            acc -= e * expm1_small(dq);
-        }
+            for (int k = 0; k < K; ++k) {
+                const float *bk = b + kBumpF * k;
+                const float A = bk[0], e2 = bk[1];
+                const float ox = P.x - bk[2], oy = P.y - bk[3], oz = P.z - bk[4];
+                const float r2 = ox * ox + oy * oy + oz * oz;
+                const float E = __builtin_amdgcn_exp2f(r2 * e2);  // exp(-r^2 / (2 sigma^2))
+                nn += A * E;
+                const float w = E * bk[5];  // A E / sigma^2
+                gx -= w * ox;
+                gy -= w * oy;
+                gz -= w * oz;
+                const float y = __builtin_fmaf(ox, s.x, __builtin_fmaf(oy, s.y, __builtin_fmaf(oz, s.z, hs2)));
+                float pa;  // A expm1(y / sigma^2)
+                if constexpr (decltype(deg)::value == 3)
+                    pa = y * (bk[5] + y * (bk[6] + y * bk[7]));
+                else
+                    pa = y * (bk[5] + y * (bk[6] + y * (bk[7] + y * (bk[8] + y * bk[9]))));
+                acc -= E * pa;
+            }
+        };
+        if (dL0 <= mf.q[1])
+            bump_loop(std::integral_constant<int, 3>{});
+        else
+            bump_loop(std::integral_constant<int, 5>{});
         n = nn;
         g = mkf(gx, gy, gz);
         dn = acc;

@@ -60,6 +60,7 @@ struct vrt_medium_s {
     vrt_context_t ctx = nullptr;
     MediumDev dev{};
     MedF mf{};
+    double fp32_max_dL0 = INFINITY;  // longest step the single-precision path accepts
     BoundaryDev bnd{};
     size_t bytes = 0;
     std::vector<void *> allocs;
@@ -315,7 +316,7 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
         d.K = K;
         std::vector<double> bd((size_t)kBumpD * (K > 0 ? K : 1), 0.0);
         std::vector<float> bf((size_t)kBumpF * (K > 0 ? K : 1), 0.0f);
-        double amp = 0.0;
+        double amp = 0.0, sig_min = INFINITY;
         for (int k = 0; k < K; ++k) {
             const double *q = p + 2 + 5 * k;
             if (!(q[1] > 0.0)) {
@@ -323,20 +324,18 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
                 return fail(VRT_EINVAL, "gaussian bump %d: sigma must be > 0", k);
             }
             amp += fabs(q[0]);
+            sig_min = fmin(sig_min, q[1]);
             for (int i = 0; i < 5; ++i) bd[(size_t)kBumpD * k + i] = q[i];
-            const double is2 = 1.0 / (q[1] * q[1]);
-            float *o = bf.data() + (size_t)kBumpF * k;
-            o[0] = (float)q[0];
-            o[1] = (float)(-0.5 * is2 / log(2.0));
-            o[2] = (float)q[2];
-            o[3] = (float)q[3];
-            o[4] = (float)q[4];
-            o[5] = (float)is2;
+            fill_bump_f(q, bf.data() + (size_t)kBumpF * k);
         }
         if (!(p[0] - amp > 0.0)) {
             delete m;
             return fail(VRT_EINVAL, "gaussian medium: n0 - sum|A| must be > 0");
         }
+        // step bounds of the single-precision index difference (media.h)
+        const double nmin_sig = (p[0] - amp) * sig_min;
+        f.q[1] = (float)(kGaussRho3 * nmin_sig);
+        m->fp32_max_dL0 = kGaussRhoMax * nmin_sig;
         void *pd = nullptr, *pf = nullptr;
         if ((rc = dev_alloc(m, &pd, bd.size() * sizeof(double))) ||
             (rc = dev_alloc(m, &pf, bf.size() * sizeof(float)))) {
@@ -470,6 +469,11 @@ int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, s
     if (p->precision != VRT_FP64 && p->precision != VRT_FP32_COMP)
         return fail(VRT_EINVAL, "vrt_trace: unknown precision %d", p->precision);
     if (n_rays >= (1ull << 31)) return fail(VRT_EINVAL, "vrt_trace: n_rays must be < 2^31");
+    if (p->precision == VRT_FP32_COMP && p->dL0 > m->fp32_max_dL0)
+        return fail(VRT_EINVAL,
+                    "vrt_trace: dL0 = %g exceeds %g, the longest step the single-precision path "
+                    "keeps accurate in this medium (0.05 n_min sigma_min); use VRT_FP64",
+                    p->dL0, m->fp32_max_dL0);
     if (n_rays == 0) return VRT_OK;
     const size_t es = p->precision == VRT_FP64 ? 8 : 4;
     const void *ptrs[] = {rays->px, rays->py, rays->pz, rays->dx, rays->dy, rays->dz,

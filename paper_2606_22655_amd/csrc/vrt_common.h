@@ -22,11 +22,29 @@ struct BoundaryDev {
     float pf[6];  // the same parameters rounded to float (per-step inside test)
 };
 
-// Per-bump single-precision record of the Gaussian-sum medium:
-// A, -log2(e)/(2 sigma^2), cx, cy, cz, 1/sigma^2  (6 floats); the double
-// record is the raw (A, sigma, cx, cy, cz).
-constexpr int kBumpF = 6;
+// Per-bump single-precision record of the Gaussian-sum medium (10 floats):
+// A, -log2(e)/(2 sigma^2), cx, cy, cz, then the Taylor coefficients of
+// A expm1(y / sigma^2) in y:  A/sigma^2, A/(2 sigma^4), A/(6 sigma^6),
+// A/(24 sigma^8), A/(120 sigma^10).  The double record is the raw
+// (A, sigma, cx, cy, cz).
+constexpr int kBumpF = 10;
 constexpr int kBumpD = 5;
+
+// Fill one single-precision bump record from (A, sigma, cx, cy, cz).
+__host__ __device__ inline void fill_bump_f(const double *q, float *o) {
+    const double is2 = 1.0 / (q[1] * q[1]);
+    o[0] = (float)q[0];
+    o[1] = (float)(-0.5 * is2 / 0.69314718055994530942);  // -log2(e) / (2 sigma^2)
+    o[2] = (float)q[2];
+    o[3] = (float)q[3];
+    o[4] = (float)q[4];
+    double c = q[0];
+    const double fact[5] = {1.0, 2.0, 6.0, 24.0, 120.0};
+    for (int j = 0; j < 5; ++j) {
+        c *= is2;
+        o[5 + j] = (float)(c / fact[j]);
+    }
+}
 
 struct MediumDev {
     int kind;        // vrt_medium_kind
