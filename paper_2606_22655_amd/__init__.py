@@ -76,6 +76,12 @@ def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"libvrt.so is not built ({path}); run "
                           "`python -m paper_2606_22655_amd.build` first")
+    # torch ships its own HIP runtime under the same soname as the system one
+    # libvrt.so links against; whichever is loaded first serves the process.
+    # Load torch's first so that both share one runtime (streams and device
+    # pointers pass between them), and torch still finds its devices.
+    import torch  # noqa: F401
+
     lib = C.CDLL(path)
     vp, i32 = C.c_void_p, C.c_int
     lib.vrt_abi_version.restype = i32
