@@ -51,7 +51,8 @@ enum vrt_error {
     VRT_EINVAL = -1,       /* bad argument: null/misaligned pointer, dL0 <= 0, n <= 0, NaN parameter */
     VRT_ENOMEM = -2,       /* device allocation failed */
     VRT_EHIP = -3,         /* HIP runtime error; the message carries hipGetErrorString */
-    VRT_EUNSUPPORTED = -4  /* valid request this build does not implement */
+    VRT_EUNSUPPORTED = -4, /* valid request this build does not implement */
+    VRT_ETIMEOUT = -5      /* vrt_server_wait: the job is not done yet */
 };
 
 /* medium kinds (index distributions n(P)) */
@@ -186,9 +187,11 @@ int vrt_medium_device_bytes(vrt_medium_t m, size_t *out);
 
 /* Trace n_rays rays (asynchronous on `stream`).  n_rays may be 0 (no-op).
  * Errors (nothing is launched): EINVAL for null/misaligned pointers, dL0 <= 0,
- * max_steps <= 0, reserved != 0, unknown precision, n_rays >= 2^32;
- * EUNSUPPORTED for combinations this build does not implement; EHIP for
- * launch failures. */
+ * max_steps <= 0, max_lanes < 0 (or != 0 with VRT_FP64), unknown precision,
+ * n_rays >= 2^31, and for VRT_FP32_COMP in a Gaussian-sum medium a dL0 above
+ * 0.05 n_min sigma_min (the single-precision index difference is kept to its
+ * stated accuracy only below that); EUNSUPPORTED for combinations this build
+ * does not implement; EHIP for launch failures. */
 int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, size_t n_rays,
               void *stream);
 
@@ -197,6 +200,87 @@ int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, s
  * synchronises that stream.  Errors: EINVAL, EHIP. */
 int vrt_reduce_counters(vrt_context_t ctx, const vrt_rays *rays, size_t n_rays,
                         vrt_counters *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of trace jobs.
+ *
+ * A server owns a pool of device memory of `hbm_budget` bytes and one
+ * persistent kernel that marches the rays of every admitted job (FP32_COMP
+ * only).  A job is a batch of rays against one medium already resident on
+ * the device, given in HOST memory (vrt_rays with host pointers, float
+ * elements; pinned memory gives the fastest copies).  Jobs are admitted in
+ * submission order as soon as their rays fit in the pool (68 bytes per ray)
+ * and a job slot is free; an admitted job's inputs are copied in, and the
+ * running kernel picks it up while it still marches earlier jobs: the waves
+ * of the kernel move to the next job with unclaimed rays as their lanes run
+ * dry, so the work of jobs overlaps on the device.  When the last ray of a
+ * job retires, its outputs are copied back into the job's host arrays and
+ * the job is done.  Each ray's result is the same as vrt_trace with
+ * VRT_FP32_COMP gives it (same per-ray arithmetic), whatever else runs.
+ * Relaunches of the persistent kernel (after it idled out) replay a captured
+ * hipGraph.  Host scheduling runs on a thread owned by the server.
+ *
+ * Not from the paper: the paper traces rays one at a time; this is the batch
+ * scheduling of its per-ray march (Sec. II).
+ * --------------------------------------------------------------------------- */
+typedef struct vrt_server_s *vrt_server_t;
+
+enum vrt_job_state {
+    VRT_JOB_QUEUED = 0,   /* waiting for pool space / a job slot */
+    VRT_JOB_STAGED = 1,   /* inputs being copied to the device */
+    VRT_JOB_RUNNING = 2,  /* published to the persistent kernel */
+    VRT_JOB_COPYING = 3,  /* all rays retired, outputs being copied back */
+    VRT_JOB_DONE = 4
+};
+
+typedef struct {
+    int32_t state;        /* vrt_job_state */
+    int32_t error;        /* 0, or the VRT_E* code the job failed with */
+    uint64_t n_rays;
+    uint64_t ray_steps;   /* sum of per-ray steps (valid when DONE) */
+    double t_submit;      /* seconds on the server's steady clock */
+    double t_admit;       /* pool space granted, input copy issued */
+    double t_start;       /* visible to the kernel */
+    double t_retired;     /* last ray retired (observed by the host) */
+    double t_done;        /* outputs in host memory */
+} vrt_job_info;
+
+typedef struct {
+    uint64_t jobs_submitted, jobs_done, rays_done, ray_steps_done;
+    uint64_t kernel_launches;   /* persistent-kernel runs (graph replays) */
+    uint64_t pool_bytes, pool_peak_bytes;
+    uint32_t job_slots, lanes;  /* job-table capacity, persistent lanes per run */
+} vrt_server_stats;
+
+/* Create a server on ctx with a device pool of hbm_budget bytes (>= 1 MiB,
+ * allocated once here; nothing is allocated per job).  max_lanes caps the
+ * persistent lanes (0 = as many as the device keeps resident).  Errors:
+ * EINVAL, ENOMEM, EHIP. */
+int vrt_server_create(vrt_context_t ctx, size_t hbm_budget, int max_lanes, vrt_server_t *out);
+
+/* Submit a job: n_rays rays of `host_rays` (host pointers, float elements,
+ * layout as vrt_rays; inputs read and outputs written by the server until the
+ * job is DONE) against medium m, which must stay alive until then (its
+ * destruction is refused meanwhile).  p->precision must be VRT_FP32_COMP and
+ * p->max_lanes 0.  *job receives the job id.  Errors: EINVAL (arguments, a
+ * job larger than the whole pool, medium of another context), the same
+ * parameter checks as vrt_trace. */
+int vrt_server_submit(vrt_server_t s, vrt_medium_t m, const vrt_trace_params *p,
+                      const vrt_rays *host_rays, size_t n_rays, uint64_t *job);
+
+/* State of a job (non-blocking).  Errors: EINVAL (unknown job). */
+int vrt_server_query(vrt_server_t s, uint64_t job, vrt_job_info *out);
+
+/* Block until the job is DONE or timeout_s seconds passed (< 0: no limit).
+ * Returns VRT_OK when done, VRT_ETIMEOUT otherwise (*out filled either way). */
+int vrt_server_wait(vrt_server_t s, uint64_t job, double timeout_s, vrt_job_info *out);
+
+/* Totals since creation. */
+int vrt_server_stats_get(vrt_server_t s, vrt_server_stats *out);
+
+/* Wait for every submitted job, stop the kernel and free the pool.
+ * Errors: EHIP. */
+int vrt_server_destroy(vrt_server_t s);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *vrt_last_error(void);

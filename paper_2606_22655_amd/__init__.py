@@ -19,7 +19,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvrt.so")
 
-VRT_OK, VRT_EINVAL, VRT_ENOMEM, VRT_EHIP, VRT_EUNSUPPORTED = 0, -1, -2, -3, -4
+VRT_OK, VRT_EINVAL, VRT_ENOMEM, VRT_EHIP, VRT_EUNSUPPORTED, VRT_ETIMEOUT = 0, -1, -2, -3, -4, -5
 MEDIUM_KINDS = {"homogeneous": 0, "linear": 1, "luneburg": 2, "fiber": 3, "gaussian": 4, "grid": 5}
 BOUNDARY_KINDS = {"box": 0, "sphere": 1, "cylinder": 2}
 VRT_FP64, VRT_FP32_COMP = 0, 1
@@ -31,7 +31,10 @@ FLAG_NEAR_GRAZING = 32
 
 EXPORTED = ["vrt_abi_version", "vrt_context_create", "vrt_context_destroy",
             "vrt_medium_create_analytic", "vrt_medium_create_grid", "vrt_medium_destroy",
-            "vrt_medium_device_bytes", "vrt_trace", "vrt_reduce_counters", "vrt_last_error"]
+            "vrt_medium_device_bytes", "vrt_trace", "vrt_reduce_counters", "vrt_last_error",
+            "vrt_server_create", "vrt_server_submit", "vrt_server_query", "vrt_server_wait",
+            "vrt_server_stats_get", "vrt_server_destroy"]
+JOB_STATES = {0: "QUEUED", 1: "STAGED", 2: "RUNNING", 3: "COPYING", 4: "DONE"}
 
 
 class VrtError(RuntimeError):
@@ -63,6 +66,19 @@ COUNTER_FIELDS = ["rays", "steps", "exited", "missed", "truncated", "no_plane", 
 
 class vrt_counters(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in COUNTER_FIELDS]
+
+
+class vrt_job_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("error", C.c_int32), ("n_rays", C.c_uint64),
+                ("ray_steps", C.c_uint64), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_start", C.c_double), ("t_retired", C.c_double), ("t_done", C.c_double)]
+
+
+class vrt_server_stats(C.Structure):
+    _fields_ = [("jobs_submitted", C.c_uint64), ("jobs_done", C.c_uint64),
+                ("rays_done", C.c_uint64), ("ray_steps_done", C.c_uint64),
+                ("kernel_launches", C.c_uint64), ("pool_bytes", C.c_uint64),
+                ("pool_peak_bytes", C.c_uint64), ("job_slots", C.c_uint32), ("lanes", C.c_uint32)]
 
 
 _lib = None
@@ -97,6 +113,13 @@ def load_library(path=LIB_PATH):
     lib.vrt_trace.argtypes = [vp, C.POINTER(vrt_trace_params), C.POINTER(vrt_rays), C.c_size_t, vp]
     lib.vrt_reduce_counters.argtypes = [vp, C.POINTER(vrt_rays), C.c_size_t,
                                         C.POINTER(vrt_counters), vp]
+    lib.vrt_server_create.argtypes = [vp, C.c_size_t, i32, C.POINTER(vp)]
+    lib.vrt_server_submit.argtypes = [vp, vp, C.POINTER(vrt_trace_params), C.POINTER(vrt_rays),
+                                      C.c_size_t, C.POINTER(C.c_uint64)]
+    lib.vrt_server_query.argtypes = [vp, C.c_uint64, C.POINTER(vrt_job_info)]
+    lib.vrt_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(vrt_job_info)]
+    lib.vrt_server_stats_get.argtypes = [vp, C.POINTER(vrt_server_stats)]
+    lib.vrt_server_destroy.argtypes = [vp]
     lib.vrt_last_error.restype = C.c_char_p
     lib.vrt_last_error.argtypes = []
     for name in EXPORTED:
@@ -165,6 +188,48 @@ def vrt_medium_device_bytes(m):
 def vrt_trace(medium, params, rays, n_rays, stream):
     return _check(load_library().vrt_trace(medium, C.byref(params), C.byref(rays), int(n_rays),
                                            C.c_void_p(stream)))
+
+
+def vrt_server_create(ctx, hbm_budget, max_lanes=0):
+    h = C.c_void_p()
+    _check(load_library().vrt_server_create(ctx, int(hbm_budget), int(max_lanes), C.byref(h)))
+    return h
+
+
+def vrt_server_submit(server, medium, params, host_rays, n_rays):
+    job = C.c_uint64()
+    _check(load_library().vrt_server_submit(server, medium, C.byref(params), C.byref(host_rays),
+                                            int(n_rays), C.byref(job)))
+    return job.value
+
+
+def _info(i):
+    return {"state": JOB_STATES.get(i.state, i.state), "error": i.error, "n_rays": i.n_rays,
+            "ray_steps": i.ray_steps, "t_submit": i.t_submit, "t_admit": i.t_admit,
+            "t_start": i.t_start, "t_retired": i.t_retired, "t_done": i.t_done}
+
+
+def vrt_server_query(server, job):
+    i = vrt_job_info()
+    _check(load_library().vrt_server_query(server, int(job), C.byref(i)))
+    return _info(i)
+
+
+def vrt_server_wait(server, job, timeout_s=-1.0):
+    """Returns the job's info; raises VrtError(VRT_ETIMEOUT) if not done in time."""
+    i = vrt_job_info()
+    _check(load_library().vrt_server_wait(server, int(job), float(timeout_s), C.byref(i)))
+    return _info(i)
+
+
+def vrt_server_stats_get(server):
+    st = vrt_server_stats()
+    _check(load_library().vrt_server_stats_get(server, C.byref(st)))
+    return {k: int(getattr(st, k)) for k, _ in vrt_server_stats._fields_}
+
+
+def vrt_server_destroy(server):
+    _check(load_library().vrt_server_destroy(server))
 
 
 def vrt_reduce_counters(ctx, rays, n_rays, stream):
@@ -303,3 +368,67 @@ def trace_numpy(spec, rays, params, precision="fp32c", device=0):
     finally:
         med.close()
         ctx.close()
+
+
+class HostRays:
+    """Structure-of-arrays HOST buffers of one served job (pinned float32 for
+    the inputs and outputs, uint32 for the per-ray words)."""
+
+    def __init__(self, P0, d0, pin=True):
+        torch = _torch()
+        P0 = torch.as_tensor(P0, dtype=torch.float32)
+        d0 = torch.as_tensor(d0, dtype=torch.float32)
+        n = P0.shape[0]
+        self.n = n
+        self.inp = torch.empty((6, n), dtype=torch.float32, pin_memory=pin)
+        self.inp[0:3].copy_(P0.T)
+        self.inp[3:6].copy_(d0.T)
+        self.out = torch.empty((6, n), dtype=torch.float32, pin_memory=pin)
+        self.u32 = torch.empty((5, n), dtype=torch.int32, pin_memory=pin)
+        self.rays = vrt_rays()
+        for i, k in enumerate(("px", "py", "pz", "dx", "dy", "dz")):
+            setattr(self.rays, k, self.inp[i].data_ptr())
+        for i, k in enumerate(("ox", "oy", "oz", "odx", "ody", "odz")):
+            setattr(self.rays, k, self.out[i].data_ptr())
+        for i, k in enumerate(("status", "steps", "n_tir", "n_btir", "flags")):
+            setattr(self.rays, k, self.u32[i].data_ptr())
+
+    def results(self):
+        """Exit state as numpy arrays (valid once the job is DONE)."""
+        o = self.out.double().numpy()
+        u = self.u32.numpy().view("uint32")
+        return {"P": o[0:3].T.copy(), "D": o[3:6].T.copy(), "status": u[0].copy(),
+                "steps": u[1].copy(), "ntir": u[2].copy(), "nbtir": u[3].copy(),
+                "flags": u[4].copy()}
+
+
+class Server:
+    """Continuous batching of trace jobs on one device (FP32 + compensation):
+    a pool of hbm_budget bytes, a persistent kernel, a host scheduler thread."""
+
+    def __init__(self, ctx, hbm_budget, max_lanes=0):
+        self.handle = vrt_server_create(ctx.handle, hbm_budget, max_lanes)
+        self._keep = {}
+
+    def submit(self, medium, host_rays, params):
+        job = vrt_server_submit(self.handle, medium.handle, make_params(params, "fp32c"),
+                                host_rays.rays, host_rays.n)
+        self._keep[job] = host_rays  # host buffers must outlive the job
+        return job
+
+    def wait(self, job, timeout_s=-1.0):
+        info = vrt_server_wait(self.handle, job, timeout_s)
+        self._keep.pop(job, None)
+        return info
+
+    def query(self, job):
+        return vrt_server_query(self.handle, job)
+
+    def stats(self):
+        return vrt_server_stats_get(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            vrt_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "dispatch.h"
+#include "api_internal.h"
 
 using namespace vrt;
 
@@ -20,7 +20,7 @@ using namespace vrt;
 // ---------------------------------------------------------------------------
 static thread_local std::string g_err;
 
-static int fail(int code, const char *fmt, ...) {
+int vrt::fail(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -29,46 +29,9 @@ static int fail(int code, const char *fmt, ...) {
     g_err = buf;
     return code;
 }
-static int fail_hip(hipError_t e, const char *what) {
+int vrt::fail_hip(hipError_t e, const char *what) {
     return fail(e == hipErrorOutOfMemory ? VRT_ENOMEM : VRT_EHIP, "%s: %s", what,
                 hipGetErrorString(e));
-}
-#define HIP_TRY(call, what)                                  \
-    do {                                                     \
-        hipError_t e_ = (call);                              \
-        if (e_ != hipSuccess) return fail_hip(e_, (what));   \
-    } while (0)
-
-// ---------------------------------------------------------------------------
-// handles
-// ---------------------------------------------------------------------------
-static constexpr int kQueueSlots = 1024;
-static constexpr int kQueueStride = 16;  // uint32 per slot: one 64-byte line each
-static constexpr int kNumCounters = 15;
-
-struct vrt_context_s {
-    int device = 0;
-    int num_cu = 256;
-    uint32_t *queues = nullptr;  // kQueueSlots ray-queue counters
-    unsigned long long *counters = nullptr;
-    std::atomic<uint32_t> next_slot{0};
-    std::atomic<int> n_media{0};
-    std::mutex counters_mu;
-};
-
-struct vrt_medium_s {
-    vrt_context_t ctx = nullptr;
-    MediumDev dev{};
-    MedF mf{};
-    double fp32_max_dL0 = INFINITY;  // longest step the single-precision path accepts
-    BoundaryDev bnd{};
-    size_t bytes = 0;
-    std::vector<void *> allocs;
-};
-
-static int set_device(vrt_context_t c) {
-    HIP_TRY(hipSetDevice(c->device), "hipSetDevice");
-    return VRT_OK;
 }
 
 static int dev_alloc(vrt_medium_t m, void **p, size_t bytes) {
@@ -193,6 +156,9 @@ int vrt_context_destroy(vrt_context_t ctx) {
     if (!ctx) return fail(VRT_EINVAL, "vrt_context_destroy: NULL context");
     if (ctx->n_media.load() != 0)
         return fail(VRT_EINVAL, "vrt_context_destroy: %d media still alive", ctx->n_media.load());
+    if (ctx->n_servers.load() != 0)
+        return fail(VRT_EINVAL, "vrt_context_destroy: %d servers still alive",
+                    ctx->n_servers.load());
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(ctx->queues);
@@ -438,6 +404,9 @@ int vrt_medium_create_grid(vrt_context_t ctx, const float *values, int nx, int n
 
 int vrt_medium_destroy(vrt_medium_t m) {
     if (!m) return fail(VRT_EINVAL, "vrt_medium_destroy: NULL medium");
+    if (m->jobs.load() != 0)
+        return fail(VRT_EINVAL, "vrt_medium_destroy: %d server jobs on it are not done",
+                    m->jobs.load());
     vrt_context_t ctx = m->ctx;
     (void)hipSetDevice(ctx->device);
     hipError_t e = hipDeviceSynchronize();

@@ -54,9 +54,11 @@ def test_struct_layouts_match_header(vrt, tmp_path):
 #include <stddef.h>
 #include "vrt.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(vrt_boundary), sizeof(vrt_trace_params),
-         sizeof(vrt_rays), sizeof(vrt_counters), offsetof(vrt_trace_params, precision),
-         offsetof(vrt_rays, status), offsetof(vrt_boundary, params));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(vrt_boundary),
+         sizeof(vrt_trace_params), sizeof(vrt_rays), sizeof(vrt_counters),
+         offsetof(vrt_trace_params, precision), offsetof(vrt_rays, status),
+         offsetof(vrt_boundary, params), sizeof(vrt_job_info), offsetof(vrt_job_info, t_done),
+         sizeof(vrt_server_stats), offsetof(vrt_server_stats, lanes));
   return 0;
 }
 """)
@@ -67,7 +69,9 @@ int main(void) {
                                           check=True).stdout.split()]
     want = [C.sizeof(vrt.vrt_boundary), C.sizeof(vrt.vrt_trace_params), C.sizeof(vrt.vrt_rays),
             C.sizeof(vrt.vrt_counters), vrt.vrt_trace_params.precision.offset,
-            vrt.vrt_rays.status.offset, vrt.vrt_boundary.params.offset]
+            vrt.vrt_rays.status.offset, vrt.vrt_boundary.params.offset,
+            C.sizeof(vrt.vrt_job_info), vrt.vrt_job_info.t_done.offset,
+            C.sizeof(vrt.vrt_server_stats), vrt.vrt_server_stats.lanes.offset]
     assert got == want
 
 
@@ -84,7 +88,9 @@ def test_enums_match_header(vrt):
     for k, v in vrt.STATUS.items():
         assert val("VRT_RAY_" + k) == v
     assert val("VRT_FP64") == vrt.VRT_FP64 and val("VRT_FP32_COMP") == vrt.VRT_FP32_COMP
-    assert val("VRT_EINVAL") == vrt.VRT_EINVAL
+    assert val("VRT_EINVAL") == vrt.VRT_EINVAL and val("VRT_ETIMEOUT") == vrt.VRT_ETIMEOUT
+    for k, v in vrt.JOB_STATES.items():
+        assert val("VRT_JOB_" + v) == k
 
 
 def test_product_path_does_not_reference_the_oracle():

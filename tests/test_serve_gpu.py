@@ -1,0 +1,194 @@
+"""Served continuous batching (vrt_server_*): jobs of uneven ray counts against
+several device-resident media, admitted by a device pool budget, marched by
+one persistent kernel.  Checks: every ray of a job in the mix equals the same
+job served alone (bitwise), served results meet the parity bar against the
+FP64 oracle, admission under a small pool, relaunch of the idled-out kernel,
+and the API's refusals."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads
+from parity import assert_parity, compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vrt():
+    import torch
+
+    import paper_2606_22655_amd as vrt
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    vrt.load_library()
+    return vrt
+
+
+@pytest.fixture(scope="module")
+def ctx(vrt):
+    c = vrt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def media(vrt, ctx):
+    """Five media: Gaussian-bump cube, 48^3 quantized grid, Luneburg sphere,
+    fiber cylinder, linear slab."""
+    specs = [workloads.gaussian_medium(500), workloads.grid_medium(workloads.noise_grid(48, 504))]
+    lun, _, _ = workloads.luneburg_beam(n_side=4)
+    specs.append(lun)
+    specs.append({"kind": "fiber", "params": np.array([1.38, 0.2, 5.0, 0.0, 0.0]),
+                  "boundary": {"kind": "cylinder", "params": np.array([0, 0, 5.0, 0.0, 10.0])},
+                  "n_amb": 1.068943})
+    specs.append({"kind": "linear", "params": np.array([1.5, 0.05, -0.02, 0.1]),
+                  "boundary": {"kind": "box", "params": np.array([0, 0, 0, 1, 1, 1.0])},
+                  "n_amb": 1.0})
+    meds = [vrt.Medium(ctx, s) for s in specs]
+    yield specs, meds
+    for m in meds:
+        m.close()
+
+
+def job_rays(spec, n, seed):
+    """Launch states for a job against `spec` (face or beam launches)."""
+    kind = spec["boundary"]["kind"]
+    if kind == "box":
+        return workloads.face_cone_rays(n, seed, 25.0)
+    rng = np.random.default_rng(seed)
+    if kind == "sphere":
+        h = rng.uniform(-0.9, 0.9, (n, 2))
+        return np.column_stack([h, np.full(n, -1.5)]), np.tile([0.0, 0.0, 1.0], (n, 1))
+    r = rng.uniform(0.0, 4.0, n)
+    a = rng.uniform(0.0, 2 * np.pi, n)
+    P0 = np.column_stack([r * np.cos(a), r * np.sin(a), np.full(n, -0.5)])
+    th = np.radians(rng.uniform(0.0, 30.0, n))
+    ph = rng.uniform(0.0, 2 * np.pi, n)
+    d0 = np.column_stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+    return P0.astype(np.float32).astype(np.float64), d0.astype(np.float32).astype(np.float64)
+
+
+def params_for(spec):
+    dL0 = 2e-3 if spec["kind"] == "fiber" else 5e-4
+    return workloads.trace_params(dL0, 60000)
+
+
+def serve_all(vrt, ctx, meds, jobs, budget=1 << 30, max_lanes=0):
+    srv = vrt.Server(ctx, budget, max_lanes)
+    try:
+        bufs = [vrt.HostRays(P0, d0) for (_, (P0, d0), _) in jobs]
+        ids = [srv.submit(meds[mi], b, prm) for (mi, _, prm), b in zip(jobs, bufs)]
+        infos = [srv.wait(j, 120.0) for j in ids]
+        stats = srv.stats()
+    finally:
+        srv.close()
+    return [b.results() for b in bufs], infos, stats
+
+
+def mixed_jobs(specs, seed, sizes):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, n in enumerate(sizes):
+        mi = int(rng.integers(0, len(specs)))
+        out.append((mi, job_rays(specs[mi], n, 1000 * seed + k), params_for(specs[mi])))
+    return out
+
+
+def same(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in ("P", "D", "status", "steps", "ntir", "nbtir",
+                                                    "flags"))
+
+
+def test_job_in_mix_equals_job_alone_bitwise(vrt, ctx, media):
+    specs, meds = media
+    sizes = [1, 37, 256, 1000, 5000, 20000, 3, 12000, 640, 64, 2500, 9000]
+    jobs = mixed_jobs(specs, 1, sizes)
+    mix, infos, stats = serve_all(vrt, ctx, meds, jobs)
+    assert all(i["state"] == "DONE" and i["error"] == 0 for i in infos)
+    assert stats["jobs_done"] == len(jobs) and stats["rays_done"] == sum(sizes)
+    for k in (0, 4, 5, 7, 11):  # served one at a time
+        alone, _, _ = serve_all(vrt, ctx, meds, [jobs[k]])
+        assert same(alone[0], mix[k]), k
+    # a job's step total is the sum of its rays' steps
+    for r, i in zip(mix, infos):
+        assert i["ray_steps"] == int(r["steps"].astype(np.int64).sum())
+
+
+def test_served_results_meet_the_parity_bar(vrt, ctx, media):
+    import oracle
+
+    specs, meds = media
+    jobs = mixed_jobs(specs, 2, [3000, 2000, 4000, 1500, 2500, 3500])
+    res, _, _ = serve_all(vrt, ctx, meds, jobs)
+    for (mi, rays, prm), r in zip(jobs, res):
+        o = oracle.trace(specs[mi], rays, prm)
+        if specs[mi]["kind"] == "grid":  # chaotic medium: identical only for short marches
+            continue
+        ap = 2.0 if specs[mi]["boundary"]["kind"] == "sphere" else (
+            10.0 if specs[mi]["kind"] == "fiber" else 1.0)
+        assert_parity(compare(o, r, aperture=ap, spec=specs[mi]))
+
+
+def test_admission_under_a_small_pool(vrt, ctx, media):
+    """A 2 MiB pool holds at most ~30k rays: jobs wait for space, then run."""
+    specs, meds = media
+    sizes = [20000, 20000, 15000, 500, 25000, 800, 10000]
+    jobs = mixed_jobs(specs, 3, sizes)
+    small, infos, stats = serve_all(vrt, ctx, meds, jobs, budget=2 << 20)
+    big, _, _ = serve_all(vrt, ctx, meds, jobs)
+    assert all(same(a, b) for a, b in zip(small, big))
+    assert stats["pool_peak_bytes"] <= 2 << 20
+    # the pool forced later jobs to wait for earlier ones to finish
+    assert any(i["t_admit"] > min(x["t_done"] for x in infos[:k]) for k, i in enumerate(infos)
+               if k > 0)
+
+
+def test_kernel_relaunches_after_idling_out(vrt, ctx, media):
+    specs, meds = media
+    srv = vrt.Server(ctx, 64 << 20)
+    try:
+        P0, d0 = job_rays(specs[0], 2000, 9)
+        a, b = vrt.HostRays(P0, d0), vrt.HostRays(P0, d0)
+        srv.wait(srv.submit(meds[0], a, params_for(specs[0])), 60.0)
+        time.sleep(0.3)  # the persistent kernel leaves after ~2 ms without work
+        srv.wait(srv.submit(meds[0], b, params_for(specs[0])), 60.0)
+        assert srv.stats()["kernel_launches"] >= 2
+    finally:
+        srv.close()
+    assert same(a.results(), b.results())
+
+
+def test_lane_cap_and_many_small_jobs(vrt, ctx, media):
+    """300 small jobs on a 512-lane server equal the same jobs on the full one."""
+    specs, meds = media
+    sizes = list(np.random.default_rng(4).integers(1, 700, 300))
+    jobs = mixed_jobs(specs, 4, sizes)
+    narrow, infos, stats = serve_all(vrt, ctx, meds, jobs, max_lanes=512)
+    wide, _, _ = serve_all(vrt, ctx, meds, jobs)
+    assert stats["lanes"] == 512
+    assert all(same(a, b) for a, b in zip(narrow, wide))
+
+
+def test_server_refusals(vrt, ctx, media):
+    specs, meds = media
+    srv = vrt.Server(ctx, 1 << 20)
+    try:
+        P0, d0 = job_rays(specs[0], 100, 5)
+        h = vrt.HostRays(P0, d0)
+        prm = params_for(specs[0])
+        with pytest.raises(vrt.VrtError):  # FP64 is not served
+            vrt.vrt_server_submit(srv.handle, meds[0].handle, vrt.make_params(prm, "fp64"),
+                                  h.rays, h.n)
+        big = vrt.HostRays(*job_rays(specs[0], 20000, 6))
+        with pytest.raises(vrt.VrtError) as e:  # larger than the whole pool
+            srv.submit(meds[0], big, prm)
+        assert "pool" in vrt.vrt_last_error()
+        with pytest.raises(vrt.VrtError):
+            srv.query(123456)
+        job = srv.submit(meds[0], h, prm)
+        srv.wait(job, 60.0)
+        assert srv.query(job)["state"] == "DONE"
+    finally:
+        srv.close()
