@@ -163,12 +163,161 @@ def cpu_baseline(spec, rays, prm, sample, g_res, aperture):
     return base, {k: rep[k] for k in keys}
 
 
+# ---------------------------------------------------------------------------
+# served mix: Poisson stream of jobs against 8 resident media
+# ---------------------------------------------------------------------------
+POOL_RAYS = 1 << 22  # launch states per medium; a job takes a slice
+
+
+def served_inputs(torch, media):
+    """Per medium, 4M pinned float32 launch states (SoA rows): face launches
+    in a 20 deg (analytic) or 30 deg (grid) cone, seeds 600 + medium."""
+    pools = []
+    for i, spec in enumerate(media):
+        cone = 30.0 if spec["kind"] == "grid" else 20.0
+        P0, d0 = workloads.face_cone_rays(POOL_RAYS, 600 + i, cone)
+        t = torch.empty((6, POOL_RAYS), dtype=torch.float32, pin_memory=True)
+        t[0:3].copy_(torch.from_numpy(P0.T.astype(np.float32)))
+        t[3:6].copy_(torch.from_numpy(d0.T.astype(np.float32)))
+        pools.append(t)
+    return pools
+
+
+def job_buffers(vrt, torch, pool, off, n):
+    """vrt_rays over pinned host memory: inputs are rows of the medium's pool,
+    outputs fresh pinned arrays."""
+    out = torch.empty((6, n), dtype=torch.float32, pin_memory=True)
+    u32 = torch.empty((5, n), dtype=torch.int32, pin_memory=True)
+    r = vrt.vrt_rays()
+    for i, k in enumerate(("px", "py", "pz", "dx", "dy", "dz")):
+        setattr(r, k, pool[i].data_ptr() + 4 * off)
+    for i, k in enumerate(("ox", "oy", "oz", "odx", "ody", "odz")):
+        setattr(r, k, out[i].data_ptr())
+    for i, k in enumerate(("status", "steps", "n_tir", "n_btir", "flags")):
+        setattr(r, k, u32[i].data_ptr())
+    return r, (out, u32)
+
+
+def served_bench(vrt, torch, args):
+    """Continuous batching of a Poisson job stream (ray counts log-uniform in
+    [1e3, 4e6], 8 resident media) on the served FP32c path, then the same
+    stream on the plain one-launch-per-job FP64 march (FIFO, one job at a
+    time).  Latency = done - arrival."""
+    t_setup = time.perf_counter()
+    media = workloads.served_media()
+    ctx = vrt.Context(0)
+    meds = [vrt.Medium(ctx, m) for m in media]
+    pools = served_inputs(torch, media)
+    prm = workloads.trace_params(5e-4, 60000)
+    budget = 4 << 30
+    srv = vrt.Server(ctx, budget)
+    print(f"[served] setup {time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
+    # capacity: one 2^18-ray job per medium, all at once
+    keep, ids = [], []
+    t0 = time.perf_counter()
+    for i, m in enumerate(meds):
+        r, bufs = job_buffers(vrt, torch, pools[i], 0, 1 << 18)
+        keep.append(bufs)
+        ids.append(vrt.vrt_server_submit(srv.handle, m.handle, vrt.make_params(prm, "fp32c"), r,
+                                         1 << 18))
+    infos = [vrt.vrt_server_wait(srv.handle, j, 600.0) for j in ids]
+    cal_s = time.perf_counter() - t0
+    print("[served] calibration job ms: " + " ".join(
+        f"{1e3 * (i['t_retired'] - i['t_start']):.1f}" for i in infos) + f", total {1e3 * cal_s:.1f}",
+        file=sys.stderr, flush=True)
+    steps_per_ray = [i["ray_steps"] / (1 << 18) for i in infos]
+    cap = sum(i["ray_steps"] for i in infos) / cal_s
+    jobs0 = workloads.served_jobs(n_jobs=args.jobs)
+    mean_steps = float(np.mean([j["n_rays"] * steps_per_ray[j["medium"]] for j in jobs0]))
+    rate = args.load * cap / mean_steps
+    jobs = workloads.served_jobs(n_jobs=args.jobs, rate_hz=rate)
+    print(f"[served] capacity {cap:.3g} ray-steps/s, rate {rate:.2f} jobs/s, "
+          f"{len(jobs)} jobs, {sum(j['n_rays'] for j in jobs)} rays", file=sys.stderr, flush=True)
+
+    def offset(j):
+        return j["ray_seed"] % (POOL_RAYS - j["n_rays"] + 1)
+
+    # served run: submit at the arrival times
+    keep, ids = [], []
+    t_base = time.perf_counter()
+    for k, j in enumerate(jobs):
+        wait = j["t_arrival"] - (time.perf_counter() - t_base)
+        if wait > 0:
+            time.sleep(wait)
+        if k % 10 == 0:
+            print(f"[served] submitting job {k} at {time.perf_counter() - t_base:.2f} s",
+                  file=sys.stderr, flush=True)
+        r, bufs = job_buffers(vrt, torch, pools[j["medium"]], offset(j), j["n_rays"])
+        keep.append(bufs)
+        ids.append(vrt.vrt_server_submit(srv.handle, meds[j["medium"]].handle,
+                                         vrt.make_params(prm, "fp32c"), r, j["n_rays"]))
+    infos = [vrt.vrt_server_wait(srv.handle, jid, 600.0) for jid in ids]
+    stats = vrt.vrt_server_stats_get(srv.handle)
+    srv.close()
+    lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+    span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+    steps = sum(i["ray_steps"] for i in infos)
+    rays = sum(i["n_rays"] for i in infos)
+    served = {"rays_per_s": rays / span, "ray_steps_per_s": steps / span,
+              "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+              "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+              "span_s": span, "kernel_launches": stats["kernel_launches"],
+              "pool_peak_bytes": stats["pool_peak_bytes"], "lanes": stats["lanes"]}
+    print(f"[served] fp32c: {rays / span:.4g} rays/s, p50 {served['p50_ms']:.1f} ms, "
+          f"p99 {served['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    del keep
+    # the same stream, one FP64 launch per job, FIFO on one stream
+    stream = torch.cuda.current_stream()
+    lat64, busy = [], 0.0
+    clock = 0.0  # simulated clock on the arrival axis: a job starts at max(arrival, previous end)
+    for k, j in enumerate(jobs):
+        if k % 10 == 0:
+            print(f"[served] fp64 job {k}", file=sys.stderr, flush=True)
+        n, src = j["n_rays"], pools[j["medium"]]
+        off = offset(j)
+        t_start = time.perf_counter()
+        b = vrt.RayBatch(src[0:3, off:off + n].T.double(), src[3:6, off:off + n].T.double(), "fp64")
+        vrt.trace(meds[j["medium"]], b, prm, "fp64", stream=stream.cuda_stream)
+        _ = b.out.cpu(), b.u32.cpu()
+        dur = time.perf_counter() - t_start
+        busy += dur
+        clock = max(clock, j["t_arrival"]) + dur
+        lat64.append(clock - j["t_arrival"])
+        del b
+    lat64 = np.array(lat64)
+    fp64 = {"rays_per_s": rays / busy, "p50_ms": 1e3 * float(np.percentile(lat64, 50)),
+            "p99_ms": 1e3 * float(np.percentile(lat64, 99)), "busy_s": busy,
+            "note": "jobs run back to back on the GPU, one FP64 launch each (inputs copied in, "
+                    "outputs copied out); each job starts at max(its arrival, the previous "
+                    "job's end) on the arrival clock"}
+    print(f"[served] fp64 per job: {rays / busy:.4g} rays/s, p50 {fp64['p50_ms']:.1f} ms, "
+          f"p99 {fp64['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    for m in meds:
+        m.close()
+    ctx.close()
+    return {"metric": METRIC, "value": served["ray_steps_per_s"], "unit": "ray-steps/s",
+            "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * span,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"served mix: {len(jobs)} Poisson jobs at {rate:.2f}/s "
+                                   f"({args.load:.0%} of measured capacity), ray counts "
+                                   "log-uniform in [1e3, 4e6], 4 Gaussian-bump cubes + grids "
+                                   "128/160/192/256^3, dL0 = 5e-4, FP32 + compensation",
+                       "rays": rays, "ray_steps": steps, "pool_bytes": budget},
+            "served_fp32c": served, "one_launch_per_job_fp64": fp64,
+            "p99_speedup_vs_fp64": fp64["p99_ms"] / served["p99_ms"]}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="freeform", choices=["freeform", "grid", "luneburg"])
+    ap.add_argument("--workload", default="freeform",
+                    choices=["freeform", "grid", "luneburg", "served"])
+    ap.add_argument("--jobs", type=int, default=120, help="served: jobs in the arrival stream")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="served: offered load as a fraction of the measured capacity")
     ap.add_argument("--rays", type=int, default=None)
     ap.add_argument("--cpu-sample", type=int, default=524288)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -186,6 +335,9 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         return 1
+    if args.workload == "served":
+        print(json.dumps(served_bench(vrt, torch, args)), flush=True)
+        return 0
     spec, rays, prm, precision, desc, aperture = build_workload(args.workload, args.rays)
     n_rays = rays[0].shape[0]
     print(f"[bench] workload ready: {n_rays} rays", file=sys.stderr, flush=True)

@@ -205,20 +205,25 @@ int vrt_reduce_counters(vrt_context_t ctx, const vrt_rays *rays, size_t n_rays,
  * Serving: continuous batching of trace jobs.
  *
  * A server owns a pool of device memory of `hbm_budget` bytes and one
- * persistent kernel that marches the rays of every admitted job (FP32_COMP
- * only).  A job is a batch of rays against one medium already resident on
- * the device, given in HOST memory (vrt_rays with host pointers, float
- * elements; pinned memory gives the fastest copies).  Jobs are admitted in
- * submission order as soon as their rays fit in the pool (68 bytes per ray)
- * and a job slot is free; an admitted job's inputs are copied in, and the
- * running kernel picks it up while it still marches earlier jobs: the waves
- * of the kernel move to the next job with unclaimed rays as their lanes run
- * dry, so the work of jobs overlaps on the device.  When the last ray of a
- * job retires, its outputs are copied back into the job's host arrays and
- * the job is done.  Each ray's result is the same as vrt_trace with
- * VRT_FP32_COMP gives it (same per-ray arithmetic), whatever else runs.
- * Relaunches of the persistent kernel (after it idled out) replay a captured
- * hipGraph.  Host scheduling runs on a thread owned by the server.
+ * persistent kernel that marches the rays of every admitted job, whatever
+ * its medium kind (FP32_COMP only).  A job is a batch of rays against one
+ * medium already resident on the device, given in PINNED HOST memory
+ * (vrt_rays with host pointers into hipHostMalloc allocations, float
+ * elements).  Jobs are admitted in submission order as soon as their rays fit
+ * in the pool (68 bytes per ray) and their job slot is free; an admitted
+ * job's inputs are copied in by the SDMA copy engines, and the running kernel
+ * picks it up while it still marches earlier jobs: its waves move to the next
+ * job with unclaimed rays as their lanes run dry, so the work of jobs
+ * overlaps on the device.  When the last ray of a job retires, its outputs
+ * are copied back into the job's host arrays and the job is done.  The
+ * kernel never waits for work queued on a stream: host and kernel talk
+ * through pinned host memory, so copies and new jobs reach it while it runs.
+ * Each ray's result is the same as vrt_trace with VRT_FP32_COMP gives it
+ * (same per-ray arithmetic), whatever else runs.  The kernel leaves about
+ * 2 ms after the last job retired; relaunches replay a captured hipGraph.
+ * While it runs it occupies every compute unit it was sized for, so other
+ * kernels on the device wait for it.  Host scheduling runs on a thread owned
+ * by the server.
  *
  * Not from the paper: the paper traces rays one at a time; this is the batch
  * scheduling of its per-ray march (Sec. II).
@@ -227,10 +232,9 @@ typedef struct vrt_server_s *vrt_server_t;
 
 enum vrt_job_state {
     VRT_JOB_QUEUED = 0,   /* waiting for pool space / a job slot */
-    VRT_JOB_STAGED = 1,   /* inputs being copied to the device */
-    VRT_JOB_RUNNING = 2,  /* published to the persistent kernel */
-    VRT_JOB_COPYING = 3,  /* all rays retired, outputs being copied back */
-    VRT_JOB_DONE = 4
+    VRT_JOB_RUNNING = 1,  /* admitted: inputs copied in, then visible to the kernel */
+    VRT_JOB_COPYING = 2,  /* all rays retired, outputs being copied back */
+    VRT_JOB_DONE = 3
 };
 
 typedef struct {
@@ -239,8 +243,8 @@ typedef struct {
     uint64_t n_rays;
     uint64_t ray_steps;   /* sum of per-ray steps (valid when DONE) */
     double t_submit;      /* seconds on the server's steady clock */
-    double t_admit;       /* pool space granted, input copy issued */
-    double t_start;       /* visible to the kernel */
+    double t_admit;       /* pool space granted */
+    double t_start;       /* inputs in the pool, job handed to the kernel */
     double t_retired;     /* last ray retired (observed by the host) */
     double t_done;        /* outputs in host memory */
 } vrt_job_info;
@@ -249,22 +253,23 @@ typedef struct {
     uint64_t jobs_submitted, jobs_done, rays_done, ray_steps_done;
     uint64_t kernel_launches;   /* persistent-kernel runs (graph replays) */
     uint64_t pool_bytes, pool_peak_bytes;
-    uint32_t job_slots, lanes;  /* job-table capacity, persistent lanes per run */
+    uint32_t job_slots, lanes;  /* job-table capacity, most persistent lanes running at once */
 } vrt_server_stats;
 
 /* Create a server on ctx with a device pool of hbm_budget bytes (>= 1 MiB,
- * allocated once here; nothing is allocated per job).  max_lanes caps the
- * persistent lanes (0 = as many as the device keeps resident).  Errors:
- * EINVAL, ENOMEM, EHIP. */
+ * allocated once here; nothing is allocated per job).  The persistent kernel
+ * fills the device (all compute units at its occupancy); max_lanes caps its
+ * lanes (multiples of 256; 0 = no cap).  Errors: EINVAL, ENOMEM, EHIP. */
 int vrt_server_create(vrt_context_t ctx, size_t hbm_budget, int max_lanes, vrt_server_t *out);
 
 /* Submit a job: n_rays rays of `host_rays` (host pointers, float elements,
- * layout as vrt_rays; inputs read and outputs written by the server until the
- * job is DONE) against medium m, which must stay alive until then (its
- * destruction is refused meanwhile).  p->precision must be VRT_FP32_COMP and
- * p->max_lanes 0.  *job receives the job id.  Errors: EINVAL (arguments, a
- * job larger than the whole pool, medium of another context), the same
- * parameter checks as vrt_trace. */
+ * layout as vrt_rays, every array inside one pinned host allocation; inputs
+ * read and outputs written by the server until the job is DONE) against
+ * medium m, which must stay alive until then (its destruction is refused
+ * meanwhile).  p->precision must be VRT_FP32_COMP and p->max_lanes 0.  *job
+ * receives the job id.  Errors: EINVAL (arguments, arrays not in pinned host
+ * memory, a job larger than the whole pool, medium of another context), the
+ * same parameter checks as vrt_trace. */
 int vrt_server_submit(vrt_server_t s, vrt_medium_t m, const vrt_trace_params *p,
                       const vrt_rays *host_rays, size_t n_rays, uint64_t *job);
 

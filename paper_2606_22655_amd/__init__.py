@@ -34,7 +34,7 @@ EXPORTED = ["vrt_abi_version", "vrt_context_create", "vrt_context_destroy",
             "vrt_medium_device_bytes", "vrt_trace", "vrt_reduce_counters", "vrt_last_error",
             "vrt_server_create", "vrt_server_submit", "vrt_server_query", "vrt_server_wait",
             "vrt_server_stats_get", "vrt_server_destroy"]
-JOB_STATES = {0: "QUEUED", 1: "STAGED", 2: "RUNNING", 3: "COPYING", 4: "DONE"}
+JOB_STATES = {0: "QUEUED", 1: "RUNNING", 2: "COPYING", 3: "DONE"}
 
 
 class VrtError(RuntimeError):

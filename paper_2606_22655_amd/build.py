@@ -17,6 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvrt.so")
 SOURCES = ["vrt_api.hip", "march_fp64.hip", "march_fp32c.hip", "serve.hip"]
 ARCH = os.environ.get("VRT_OFFLOAD_ARCH", "gfx950")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 
 def hipcc_command(out, extra=()):
@@ -24,7 +25,9 @@ def hipcc_command(out, extra=()):
              "-Wall", "-Wno-unused-function", "-Wno-unused-result",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", os.path.join(HERE, "..", "include"), "-o", out] +
-            [os.path.join(CSRC, s) for s in SOURCES] + list(extra))
+            [os.path.join(CSRC, s) for s in SOURCES] +
+            # the serving copies run on the SDMA engines through the HSA runtime
+            ["-L", os.path.join(ROCM, "lib"), "-lhsa-runtime64"] + list(extra))
 
 
 def build(verbose=False):

@@ -282,8 +282,8 @@ __device__ bool lane_init(const MediumDev &m, const float4 *__restrict__ rec, co
 
 // One decision (unless pending) and one move.  Returns false when the ray
 // ended (written).
-template <int MK>
-__device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, const float *__restrict__ bumps,
+template <int MK, class BumpPtr>
+__device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, BumpPtr bumps,
                                           const float4 *__restrict__ rec, const BoundaryDev &b,
                                           const TraceDev &t, const RaysDev<float> &io, Lane &L,
                                           GridCache &gc, float dL0, float eps_tan, float mrg,

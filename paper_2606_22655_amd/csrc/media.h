@@ -173,15 +173,14 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // P: point P_i, s = P_i - P_{i-1}, n_last = n(P_{i-1}).  bumps: the Gaussian
-// table (m.bumps_f), passed from a restrict kernel argument so that its loads
-// are known not to be clobbered by the kernel's stores (scalar loads).
+// table (m.bumps_f) -- a restrict kernel argument in the batch kernel (its
+// loads are then scalar), a copy in LDS in the serving kernel.
 // MedF.q: LINEAR [n0, gx, gy, gz]; LUNEBURG [., cx, cy, cz, 1/R^2];
 // FIBER [n_c, Delta, ., cx, cy, 2 Delta n_c^2/R^2, n_clad, R^2];
 // GAUSSIAN [n0, largest dL0 for the degree-3 difference form]; others [n0]
-template <int MK>
-__device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf,
-                                      const float *__restrict__ bumps, float dL0, f3 P, f3 s,
-                                      float n_last, float &n, f3 &g, float &dn) {
+template <int MK, class BumpPtr>
+__device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf, BumpPtr bumps, float dL0,
+                                      f3 P, f3 s, float n_last, float &n, f3 &g, float &dn) {
     if constexpr (MK == VRT_MEDIUM_HOMOGENEOUS) {
         n = mf.q[0];
         g = mkf(0, 0, 0);
@@ -226,12 +225,12 @@ __device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf,
         // polynomial in y = sigma^2 dq_k whose coefficients carry A_k.
         float nn = mf.q[0], gx = 0.f, gy = 0.f, gz = 0.f, acc = 0.f;
         const float hs2 = -0.5f * dotf(s, s);
-        const float *__restrict__ b = bumps;
+        const BumpPtr b = bumps;
         const int K = m.K;
         auto bump_loop = [&](auto deg) {
 #pragma unroll 4
             for (int k = 0; k < K; ++k) {
-                const float *bk = b + kBumpF * k;
+                const BumpPtr bk = b + kBumpF * k;
                 const float A = bk[0], e2 = bk[1];
                 const float ox = P.x - bk[2], oy = P.y - bk[3], oz = P.z - bk[4];
                 const float r2 = ox * ox + oy * oy + oz * oz;

@@ -1,33 +1,58 @@
 // serve.hip -- continuous batching of trace jobs: one persistent kernel
-// marches the rays of every admitted job while a host thread admits new jobs
-// into a device pool of fixed size, publishes them to the running kernel and
-// copies finished jobs back.
+// marches the rays of every admitted job, of every medium kind, while a host
+// thread admits new jobs into a device pool of fixed size, hands them to the
+// running kernel and copies finished jobs back.
 //
-// Device protocol (per server):
-//   table[kSlots]  job descriptors (device), slot = sequence % kSlots, written
-//                  by an input copy before the job is published;
-//   ctl[kSlots]    per slot: 64-bit claim word (sequence << 32 | next ray to
-//                  hand out), rays not yet retired, sum of retired steps;
-//   sc             pinned host words: tail (jobs [0, tail) are published),
-//                  stop;
-//   done[kSlots]   pinned host records: sequence + 1 and the ray-step total of
-//                  the job that last finished in the slot.
-// A wave works on one job at a time (the medium is uniform across its lanes).
-// Its idle lanes claim rays of that job with one compare-and-swap on the claim
-// word, which also checks that the slot still holds the job; once the job has
-// no rays left to hand out and the wave's lanes have retired theirs, the wave
-// moves to the next published job with unclaimed rays.  Adopting a job is an
-// acquire at system scope (it reads the tail the host wrote), which
-// invalidates the wave's L2 so that the job's descriptor and inputs, copied in
-// while the kernel ran, are read fresh.  Retiring rays is a release at agent
-// scope before the count of unretired rays is decremented, so outputs reach
-// memory; the wave that retires the last ray of a job writes its done record
-// with a system-scope release.  A wave with no job polls the tail, sleeping
-// between polls, and leaves after kIdlePolls empty polls or when stop is set;
-// the host relaunches the kernel (a captured hipGraph) when jobs are published
-// and it is not running.
+// The running kernel never waits for anything queued on a stream: a
+// persistent kernel can hold the hardware queue (and the compute units) that
+// such work would need.  Host and kernel talk through memory only:
+//   hdesc[kSlots]  job descriptors in coherent pinned host memory, written by
+//                  the host (slot = sequence % kSlots);
+//   mb             host mailbox (coherent pinned): htail (jobs [0, htail) are
+//                  staged: descriptor written, inputs in the pool), live
+//                  (admitted jobs not yet retired), stop; and, written by the
+//                  device, lost;
+//   table, ctl     device copies of the descriptors and, per slot, a 64-bit
+//                  claim word (sequence << 32 | next ray to hand out), the
+//                  count of unretired rays and the sum of retired steps;
+//   dc             device words: dtail (jobs [0, dtail) are active on the
+//                  device), the activation lock, first_open, exiting;
+//   done[kSlots]   done records in coherent pinned host memory: sequence + 1
+//                  and the step total of the job last finished in the slot.
+// Inputs and outputs move between the job's host arrays and the pool on the
+// SDMA engines (HSA asynchronous copies), which need no compute unit and no
+// kernel queue.  The host publishes a staged job by writing its descriptor
+// and then htail.  A wave that finds htail ahead of dtail (polled at most
+// every kPollTicks) takes the activation lock, copies the new descriptors
+// into the device table, initialises their claim words and counts, and
+// releases dtail.  Seeing a new dtail is an acquire at system scope, which
+// invalidates the wave's L2 so that inputs the copy engine wrote are read
+// fresh.
+//
+// A wave works on one group at a time -- the jobs with the same medium and
+// trace parameters -- whose descriptor and Gaussian bump table it copies into
+// LDS, so the medium is uniform across its lanes and its constants are LDS
+// reads; the march of the group's medium kind is selected once per group.
+// Its idle lanes claim rays, in job order, from the group's jobs with one
+// fetch-and-add per job on the claim word, whose sequence bits confirm that
+// the slot still held the job; a lane's ray keeps its own job (inputs,
+// outputs, accounting).  Retired rays are counted per lane and accounted in
+// wave flushes (a release at system scope, so outputs reach memory, then one
+// decrement of each job's count); the lane that brings a count to zero writes
+// the done record with a system-scope release.  When its group has no rays
+// left and its lanes are empty, the wave takes the group of the first job
+// with rays left.
+//
+// Leaving is all or nothing: a wave that has polled kIdlePolls times without
+// work while no job is live (or kLingerPolls times in any case) sets exiting;
+// from then on waves claim no new rays, finish the ones they hold and leave,
+// so the kernel ends promptly and the host's next launch (a captured hipGraph
+// replay) has the whole device again.
 #include <stdio.h>
 #include <string.h>
+
+#include <hsa/hsa.h>
+#include <hsa/hsa_ext_amd.h>
 
 #include <chrono>
 #include <condition_variable>
@@ -42,9 +67,16 @@
 namespace vrt {
 namespace serve {
 
-constexpr uint32_t kSlots = 4096;   // job table ring
-constexpr size_t kDescBytes = 1024;  // one descriptor slot
-constexpr uint32_t kIdlePolls = 600; // ~2 ms of empty polls before a wave leaves
+constexpr uint32_t kSlots = 4096;       // job table ring
+constexpr size_t kDescBytes = 1024;     // one descriptor slot
+constexpr uint32_t kIdlePolls = 40;     // empty polls (backing off to ~55 us apart) before leaving
+constexpr uint32_t kLingerPolls = 20000;  // ~1 s of empty polls: leave even with jobs live
+constexpr uint32_t kDryEvery = 64;      // iterations between tail reads of a wave whose group ran dry
+constexpr uint64_t kPollTicks = 200;    // 2 us at the 100 MHz wall clock between host-tail polls
+constexpr int kRanges = 4;              // job ranges one refill may draw from
+constexpr uint32_t kScan = 64;          // jobs a refill looks ahead for its group
+constexpr uint32_t kFlushEvery = 256;   // iterations between accounting flushes
+constexpr int kServeOcc = 2;            // resident blocks per CU the kernel is compiled for
 
 struct alignas(16) JobDesc {
     MediumDev m;
@@ -55,6 +87,8 @@ struct alignas(16) JobDesc {
     uint32_t n;
     int32_t kind;
     float dL0, eps_tan, mrg, crit;
+    uint32_t group;  // jobs with the same medium and trace parameters share a group
+    uint32_t pad[3];
 };
 static_assert(sizeof(JobDesc) <= kDescBytes, "job descriptor slot");
 static_assert(sizeof(JobDesc) % 16 == 0, "descriptor copied in 16-byte pieces");
@@ -67,10 +101,21 @@ struct JobCtl {
     unsigned long long pad2;
 };
 
-struct ServeCtl {
-    uint32_t tail;
-    uint32_t stop;
-    uint32_t pad[14];
+// device words, one 64-byte line each
+struct DevCtl {
+    uint32_t dtail, pad0[15];
+    uint32_t act, pad1[15];               // activation lock
+    unsigned long long poll_t, pad2[7];   // wall clock of the last host-tail poll
+    uint32_t first_open, pad3[15];        // jobs below it have no rays to hand out
+    uint32_t exiting, pad4[15];           // the kernel is leaving: claim nothing more
+};
+
+// host mailbox (coherent pinned host memory), one 64-byte line each
+struct Mailbox {
+    uint32_t htail, pad0[15];  // host: jobs [0, htail) are staged
+    uint32_t live, pad1[15];   // host: admitted jobs not yet retired
+    uint32_t stop, pad2[15];   // host: leave
+    uint32_t lost, pad3[15];   // device: a claim met a reused slot (fatal for the server)
 };
 
 struct DoneRec {
@@ -88,162 +133,373 @@ __device__ __forceinline__ T *rfl_ptr(T *p) {
     return (T *)(((uint64_t)hi << 32) | lo);
 }
 
-template <int MK>
-__device__ __forceinline__ bool init_k(const JobDesc &D, const float4 *rec, Lane &L, GridCache &gc) {
-    return lane_init<MK>(D.m, rec, D.b, D.t, D.io, L, gc);
-}
-template <int MK>
-__device__ __forceinline__ bool step_k(const JobDesc &D, const float *bumps, const float4 *rec,
-                                       Lane &L, GridCache &gc) {
-    return lane_step<MK>(D.m, D.mf, bumps, rec, D.b, D.t, D.io, L, gc, D.dL0, D.eps_tan, D.mrg,
-                         D.crit);
-}
+using LdsF = const __attribute__((address_space(3))) float *;
+using LdsDesc = const __attribute__((address_space(3))) JobDesc *;
 
-__device__ __forceinline__ bool init_any(int kind, const JobDesc &D, const float4 *rec, Lane &L,
-                                         GridCache &gc) {
-    switch (kind) {
-    case VRT_MEDIUM_HOMOGENEOUS: return init_k<VRT_MEDIUM_HOMOGENEOUS>(D, rec, L, gc);
-    case VRT_MEDIUM_LINEAR: return init_k<VRT_MEDIUM_LINEAR>(D, rec, L, gc);
-    case VRT_MEDIUM_LUNEBURG: return init_k<VRT_MEDIUM_LUNEBURG>(D, rec, L, gc);
-    case VRT_MEDIUM_FIBER: return init_k<VRT_MEDIUM_FIBER>(D, rec, L, gc);
-    case VRT_MEDIUM_GAUSSIAN: return init_k<VRT_MEDIUM_GAUSSIAN>(D, rec, L, gc);
-    default: return init_k<VRT_MEDIUM_GRID>(D, rec, L, gc);
+// Pointers and wave-uniform progress of one wave.
+struct WaveCtx {
+    const JobDesc *hdesc;
+    JobDesc *table;
+    JobCtl *ctl;
+    DevCtl *dc;
+    Mailbox *mb;
+    DoneRec *done;
+    unsigned long long *wacc;  // two LDS words of the wave
+    int lane;
+    uint32_t jcur;  // no job below it has rays for this wave
+    uint32_t seen;  // jobs [0, seen) are known active (acquired)
+    uint32_t it;
+};
+
+// Copy the descriptors of jobs staged by the host and not yet active into the
+// device table, initialise their claim words and counts, and publish them.
+// At most one wave at a time, at most once per kPollTicks.
+__device__ __forceinline__ void maybe_activate(WaveCtx &c) {
+    const unsigned long long now = wall_clock64();
+    uint32_t go = 0;
+    if (c.lane == 0) {
+        const unsigned long long last =
+            __hip_atomic_load(&c.dc->poll_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (now - last >= kPollTicks) {
+            uint32_t z = 0;
+            go = __hip_atomic_compare_exchange_strong(&c.dc->act, &z, 1u, __ATOMIC_ACQUIRE,
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     ? 1u
+                     : 0u;
+        }
+    }
+    if (!rfl(__shfl(go, 0))) return;
+    const uint32_t ht =
+        rfl(__hip_atomic_load(&c.mb->htail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
+    const uint32_t dt =
+        rfl(__hip_atomic_load(&c.dc->dtail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    for (uint32_t j = dt; j < ht; ++j) {
+        const uint32_t sl = j % kSlots;
+        const uint4 *src = (const uint4 *)(c.hdesc + sl);
+        uint4 *dst = (uint4 *)(c.table + sl);
+        for (uint32_t q = c.lane; q < sizeof(JobDesc) / 16; q += 64) dst[q] = src[q];
+        if (c.lane == 0) {
+            __hip_atomic_store(&c.ctl[sl].steps, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c.ctl[sl].left, c.hdesc[sl].n, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c.ctl[sl].claim, (unsigned long long)j << 32, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // descriptors and counts before dtail
+    if (c.lane == 0) {
+        if (ht > dt) __hip_atomic_store(&c.dc->dtail, ht, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&c.dc->poll_t, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&c.dc->act, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
-__device__ __forceinline__ bool step_any(int kind, const JobDesc &D, const float *bumps,
-                                         const float4 *rec, Lane &L, GridCache &gc) {
-    switch (kind) {
-    case VRT_MEDIUM_HOMOGENEOUS: return step_k<VRT_MEDIUM_HOMOGENEOUS>(D, bumps, rec, L, gc);
-    case VRT_MEDIUM_LINEAR: return step_k<VRT_MEDIUM_LINEAR>(D, bumps, rec, L, gc);
-    case VRT_MEDIUM_LUNEBURG: return step_k<VRT_MEDIUM_LUNEBURG>(D, bumps, rec, L, gc);
-    case VRT_MEDIUM_FIBER: return step_k<VRT_MEDIUM_FIBER>(D, bumps, rec, L, gc);
-    case VRT_MEDIUM_GAUSSIAN: return step_k<VRT_MEDIUM_GAUSSIAN>(D, bumps, rec, L, gc);
-    default: return step_k<VRT_MEDIUM_GRID>(D, bumps, rec, L, gc);
+
+// Take up jobs activated since the wave last looked.  Returns true if any.
+__device__ __forceinline__ bool refresh_tail(WaveCtx &c) {
+    const uint32_t dt =
+        rfl(__hip_atomic_load(&c.dc->dtail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (dt <= c.seen) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // system scope: fresh descriptors and inputs
+    c.seen = dt;
+    return true;
+}
+
+__device__ __forceinline__ bool exiting(const WaveCtx &c) {
+    return __hip_atomic_load(&c.dc->exiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// Account the wave's retired rays: one release at system scope (the outputs
+// of the retired rays reach memory, where the copy engine reads them), then
+// per job one step-sum add and one decrement of its unretired count; the lane
+// that brings a count to zero writes the job's done record.  Lanes' counts
+// are summed per job in LDS.
+__device__ __forceinline__ void flush_acc(WaveCtx &c, uint32_t aslot, uint32_t &acnt,
+                                          unsigned long long &asteps) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    uint64_t pend = __ballot(acnt != 0);
+    while (pend) {
+        const int first = __ffsll((unsigned long long)pend) - 1;
+        const uint32_t s0 = rfl(__shfl(aslot, first));
+        const bool mine = acnt != 0 && aslot == s0;
+        if (c.lane == first) {
+            c.wacc[0] = 0;
+            c.wacc[1] = 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (mine) {
+            atomicAdd(&c.wacc[0], (unsigned long long)acnt);
+            atomicAdd(&c.wacc[1], asteps);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (c.lane == first) {
+            const uint32_t cnt = (uint32_t)c.wacc[0];
+            JobCtl *jc = c.ctl + s0;
+            __hip_atomic_fetch_add(&jc->steps, c.wacc[1], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t old =
+                __hip_atomic_fetch_sub(&jc->left, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (old == cnt) {  // the job's last rays
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const unsigned long long st =
+                    __hip_atomic_load(&jc->steps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t seq = (uint32_t)(
+                    __hip_atomic_load(&jc->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32);
+                __hip_atomic_store(&c.done[s0].steps, st, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&c.done[s0].seq1, seq + 1, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        if (mine) {
+            acnt = 0;
+            asteps = 0;
+        }
+        pend = __ballot(acnt != 0);
     }
 }
 
-__global__ __launch_bounds__(256, 2) void serve_kernel(const JobDesc *__restrict__ table,
-                                                       JobCtl *ctl, const ServeCtl *sc,
-                                                       DoneRec *done, uint32_t *first_open) {
-    __shared__ JobDesc wdesc[4];  // one descriptor per wave of the block
-    JobDesc &D = wdesc[threadIdx.x >> 6];
-    const int lane = __lane_id();
-    const uint64_t below = (1ull << lane) - 1ull;
+// Job jj has rays to hand out (its slot still holds it).
+__device__ __forceinline__ bool claimable(const WaveCtx &c, uint32_t jj) {
+    const uint32_t sl = jj % kSlots;
+    const unsigned long long w =
+        __hip_atomic_load(&c.ctl[sl].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (uint32_t)(w >> 32) == jj && (uint32_t)w < c.table[sl].n;
+}
+
+// March rays of the wave's group (descriptor and bump table in LDS) until
+// the group has no rays left for it and its lanes are empty.  One function
+// per medium kind, not inlined: each gets the registers of its own march
+// (inlined side by side, the kinds' marches spill).
+template <int MK>
+__device__ __attribute__((noinline)) void march_group(WaveCtx &cw, LdsDesc Dp, LdsF B,
+                                                      uint32_t group_in) {
+    WaveCtx c;  // wave-uniform copies in scalar registers
+    c.hdesc = rfl_ptr(cw.hdesc);
+    c.table = rfl_ptr(cw.table);
+    c.ctl = rfl_ptr(cw.ctl);
+    c.dc = rfl_ptr(cw.dc);
+    c.mb = rfl_ptr(cw.mb);
+    c.done = rfl_ptr(cw.done);
+    c.wacc = cw.wacc;
+    c.lane = __lane_id();
+    c.jcur = rfl(cw.jcur);
+    c.seen = rfl(cw.seen);
+    c.it = rfl(cw.it);
+    const uint32_t group = rfl(group_in);
+    const JobDesc &D = *(const JobDesc *)Dp;
+    const uint64_t below = (1ull << c.lane) - 1ull;
     Lane L;
     GridCache gc;
     gc.ci = -1;
     bool active = false;
-    uint64_t act = 0;  // wave mask of lanes holding a ray
-    uint32_t j = rfl(__hip_atomic_load(first_open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    bool have = false, exhausted = true;
-    int kind = 0;
-    uint32_t n = 0, slot = 0, idle = 0;
-    const float *bumps = nullptr;
-    const float4 *rec = nullptr;
+    uint64_t act = 0;              // wave mask of lanes holding a ray
+    uint32_t lslot = 0;            // job slot of the lane's ray
+    uint32_t aslot = 0, acnt = 0;  // retired rays not yet accounted (all of job slot aslot)
+    unsigned long long asteps = 0;
+    bool dry = false;  // the group had fewer rays than idle lanes at the last claim
+    uint32_t dry_it = 0;
     for (;;) {
-        if (!act && (!have || exhausted)) {
-            // the wave is empty: find the next published job with rays to hand out
-            if (have) ++j;
-            have = false;
-            const uint32_t tail =
-                rfl(__hip_atomic_load(&sc->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
-            while (j < tail) {
-                const uint32_t s = j % kSlots;
-                const unsigned long long c =
-                    __hip_atomic_load(&ctl[s].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t cs = rfl((uint32_t)(c >> 32)), cn = rfl((uint32_t)c);
-                if (cs == j && cn < rfl(table[s].n)) break;
-                ++j;
-                if (lane == 0) atomicMax(first_open, j);
-            }
-            if (j >= tail) {
-                if (__hip_atomic_load(&sc->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ||
-                    ++idle > kIdlePolls)
-                    break;
-                __builtin_amdgcn_s_sleep(127);
-                continue;
-            }
-            slot = j % kSlots;
-            const uint4 *src = (const uint4 *)(table + slot);
-            uint4 *dst = (uint4 *)&D;
-            for (uint32_t q = lane; q < sizeof(JobDesc) / 16; q += 64) dst[q] = src[q];
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            have = true;
-            exhausted = false;
-            idle = 0;
-            kind = (int)rfl((uint32_t)D.kind);
-            n = rfl(D.n);
-            bumps = rfl_ptr(D.m.bumps_f);
-            rec = rfl_ptr(D.m.rec);
-            gc.ci = -1;
+        const uint64_t nm = ~act;  // lanes without a ray
+        bool fresh = false, claimed = false;
+        // The tail and claim words are contended addresses: a wave whose group
+        // ran dry looks for new jobs only every kDryEvery iterations.
+        if (nm && dry && ++dry_it % kDryEvery == 0) {
+            maybe_activate(c);
+            if (refresh_tail(c) && !exiting(c)) dry = false;
         }
-        bool ended = false;
-        if (!exhausted) {
-            const uint64_t nm = ~act;  // lanes without a ray (waves are full)
-            if (nm) {
-                const uint32_t want = (uint32_t)__popcll(nm);
-                const int leader = __ffsll((unsigned long long)nm) - 1;
-                uint32_t base = 0, got = 0;
-                if (lane == leader) {
-                    unsigned long long c =
-                        __hip_atomic_load(&ctl[slot].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    for (;;) {
-                        const uint32_t cs = (uint32_t)(c >> 32), cn = (uint32_t)c;
-                        if (cs != j || cn >= n) {  // job gone or no rays left
-                            got = 0;
-                            break;
-                        }
-                        const uint32_t take = min(want, n - cn);
-                        if (__hip_atomic_compare_exchange_strong(
-                                &ctl[slot].claim, &c, c + take, __ATOMIC_RELAXED,
-                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                            base = cn;
-                            got = take;
-                            break;
+        if (nm && !dry) {
+            const uint32_t want = (uint32_t)__popcll(nm);
+            const int leader = __ffsll((unsigned long long)nm) - 1;
+            uint32_t r0 = 0, b0 = 0, c0 = 0, r1 = 0, b1 = 0, c1 = 0, r2 = 0, b2 = 0, c2 = 0,
+                     r3 = 0, b3 = 0, c3 = 0, nr = 0, jc = c.jcur, unmet = 0;
+            if (c.lane == leader) {
+                // claim, in job order, from the jobs of the wave's group
+                uint32_t need = exiting(c) ? 0u : want;
+                unmet = need == 0;
+                const uint32_t lim = min(c.seen, c.jcur + kScan);
+                for (uint32_t jj = c.jcur; need && jj < lim && nr < (uint32_t)kRanges; ++jj) {
+                    const uint32_t sl = jj % kSlots;
+                    const uint32_t nj = c.table[sl].n;
+                    const unsigned long long w =
+                        __hip_atomic_load(&c.ctl[sl].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bool gone = (uint32_t)(w >> 32) != jj || (uint32_t)w >= nj;
+                    if (!gone && c.table[sl].group == group) {
+                        // one fetch-and-add (a compare-and-swap loop here stalls every
+                        // wave on one contended word); an add past the end only takes
+                        // what is left, and n < 2^31 keeps the overshoot out of the
+                        // sequence bits.
+                        const unsigned long long o = __hip_atomic_fetch_add(
+                            &c.ctl[sl].claim, (unsigned long long)need, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+                        const uint32_t cn = (uint32_t)o;
+                        if ((uint32_t)(o >> 32) != jj) {
+                            // the slot was reused between the check and the add: the
+                            // new job lost rays it can never get back -- report it
+                            __hip_atomic_store(&c.mb->lost, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_SYSTEM);
+                            gone = true;
+                        } else if (cn >= nj) {
+                            gone = true;
+                        } else {
+                            const uint32_t take = min(need, nj - cn);
+                            if (nr == 0) { r0 = sl; b0 = cn; c0 = take; }
+                            else if (nr == 1) { r1 = sl; b1 = cn; c1 = take; }
+                            else if (nr == 2) { r2 = sl; b2 = cn; c2 = take; }
+                            else { r3 = sl; b3 = cn; c3 = take; }
+                            ++nr;
+                            need -= take;
+                            gone = cn + take >= nj;
                         }
                     }
+                    if (gone && jj == jc) {  // nothing for anyone below jc
+                        jc = jj + 1;
+                        atomicMax(&c.dc->first_open, jc);
+                    }
                 }
-                base = rfl(__shfl(base, leader));
-                got = rfl(__shfl(got, leader));
-                if (got < want) exhausted = true;
+                unmet |= need;
+            }
+            nr = rfl(__shfl(nr, leader));
+            c.jcur = rfl(__shfl(jc, leader));
+            claimed = nr != 0;
+            if (nr < (uint32_t)kRanges && rfl(__shfl(unmet, leader)))
+                dry = true;  // fewer rays than idle lanes: the group has nothing more for now
+            if (nr) {
+                // hand the ranges to the idle lanes in lane order
+                uint32_t k = (uint32_t)__popcll(nm & below);
+                const uint32_t rr[kRanges] = {rfl(__shfl(r0, leader)), rfl(__shfl(r1, leader)),
+                                              rfl(__shfl(r2, leader)), rfl(__shfl(r3, leader))};
+                const uint32_t bb[kRanges] = {rfl(__shfl(b0, leader)), rfl(__shfl(b1, leader)),
+                                              rfl(__shfl(b2, leader)), rfl(__shfl(b3, leader))};
+                const uint32_t cc[kRanges] = {rfl(__shfl(c0, leader)), rfl(__shfl(c1, leader)),
+                                              rfl(__shfl(c2, leader)), rfl(__shfl(c3, leader))};
                 if (!active) {
-                    const uint32_t k = (uint32_t)__popcll(nm & below);
-                    if (k < got) {
-                        L.r = base + k;
-                        active = init_any(kind, D, rec, L, gc);
-                        ended = !active;
+#pragma unroll
+                    for (int q = 0; q < kRanges; ++q) {
+                        if (!fresh && (uint32_t)q < nr) {
+                            if (k < cc[q]) {
+                                L.r = bb[q] + k;
+                                lslot = rr[q];
+                                fresh = true;
+                            } else {
+                                k -= cc[q];
+                            }
+                        }
                     }
                 }
             }
         }
-        if (active) {
-            active = step_any(kind, D, bumps, rec, L, gc);
+        // a lane may only start a ray of another job once its count is accounted
+        if (__ballot(fresh && acnt && aslot != lslot) || (++c.it % kFlushEvery == 0 && __ballot(acnt)))
+            flush_acc(c, aslot, acnt, asteps);
+        bool ended = false;
+        if (fresh) {
+            aslot = lslot;
+            gc.ci = -1;
+            active = lane_init<MK>(D.m, D.m.rec, D.b, D.t, c.table[lslot].io, L, gc);
             ended = !active;
         }
-        const uint64_t fin = __ballot(ended);
-        if (fin) {
-            if (ended)
-                __hip_atomic_fetch_add(&ctl[slot].steps, (unsigned long long)L.steps,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();  // outputs and step sums before the retire count
-            const int leader = __ffsll((unsigned long long)fin) - 1;
-            if (lane == leader) {
-                const uint32_t cnt = (uint32_t)__popcll(fin);
-                const uint32_t old = __hip_atomic_fetch_sub(&ctl[slot].left, cnt, __ATOMIC_ACQ_REL,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
-                if (old == cnt) {  // the job's last rays
-                    const unsigned long long st = __hip_atomic_load(
-                        &ctl[slot].steps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __threadfence_system();
-                    __hip_atomic_store(&done[slot].steps, st, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_SYSTEM);
-                    __hip_atomic_store(&done[slot].seq1, j + 1, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_SYSTEM);
-                }
-            }
+        if (active) {
+            active = lane_step<MK>(D.m, D.mf, B, D.m.rec, D.b, D.t, c.table[lslot].io, L, gc,
+                                   D.dL0, D.eps_tan, D.mrg, D.crit);
+            ended = !active;
+        }
+        if (ended) {
+            acnt++;
+            asteps += L.steps;
         }
         act = __ballot(active);
+        if (!act && (dry || !claimed)) {
+            if (__ballot(acnt)) flush_acc(c, aslot, acnt, asteps);
+            cw.jcur = c.jcur;
+            cw.seen = c.seen;
+            cw.it = c.it;
+            return;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256, kServeOcc) void serve_kernel(const JobDesc *hdesc,
+                                                               JobDesc *table, JobCtl *ctl,
+                                                               DevCtl *dc, Mailbox *mb,
+                                                               DoneRec *done) {
+    __shared__ JobDesc wdesc[4];                        // the wave's group: medium, params
+    __shared__ float wbump[4][VRT_MAX_BUMPS * kBumpF];  // its bump table
+    __shared__ unsigned long long wacc_all[4][2];
+    const int w = threadIdx.x >> 6;
+    JobDesc &D = wdesc[w];
+    const LdsF B = (LdsF)&wbump[w][0];
+    WaveCtx c;
+    c.hdesc = hdesc;
+    c.table = table;
+    c.ctl = ctl;
+    c.dc = dc;
+    c.mb = mb;
+    c.done = done;
+    c.wacc = wacc_all[w];
+    c.lane = __lane_id();
+    c.jcur = rfl(__hip_atomic_load(&dc->first_open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    c.seen = 0;
+    c.it = 0;
+    uint32_t idle = 0;
+    for (;;) {
+        // the wave is empty and accounted: find the first job with rays left
+        maybe_activate(c);
+        refresh_tail(c);
+        if (exiting(c)) break;
+        uint32_t fo =
+            rfl(__hip_atomic_load(&dc->first_open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (fo > c.jcur) c.jcur = fo;
+        while (c.jcur < c.seen && !claimable(c, c.jcur)) {
+            if (c.jcur == fo) {
+                fo = c.jcur + 1;
+                if (c.lane == 0) atomicMax(&dc->first_open, fo);
+            }
+            ++c.jcur;
+        }
+        if (c.jcur < c.seen) {
+            // adopt the job's group: its descriptor and bump table into LDS
+            const uint32_t sl = c.jcur % kSlots;
+            const uint4 *src = (const uint4 *)(table + sl);
+            uint4 *dst = (uint4 *)&D;
+            for (uint32_t q = c.lane; q < sizeof(JobDesc) / 16; q += 64) dst[q] = src[q];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const int kind = (int)rfl((uint32_t)D.kind);
+            const uint32_t nb = kind == VRT_MEDIUM_GAUSSIAN ? rfl((uint32_t)D.m.K) * kBumpF : 0u;
+            const float *bsrc = D.m.bumps_f;
+            for (uint32_t q = c.lane; q < nb; q += 64) wbump[w][q] = bsrc[q];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t group = rfl(D.group);
+            const LdsDesc Dl = (LdsDesc)&wdesc[w];
+            switch (kind) {
+            case VRT_MEDIUM_HOMOGENEOUS: march_group<VRT_MEDIUM_HOMOGENEOUS>(c, Dl, B, group); break;
+            case VRT_MEDIUM_LINEAR: march_group<VRT_MEDIUM_LINEAR>(c, Dl, B, group); break;
+            case VRT_MEDIUM_LUNEBURG: march_group<VRT_MEDIUM_LUNEBURG>(c, Dl, B, group); break;
+            case VRT_MEDIUM_FIBER: march_group<VRT_MEDIUM_FIBER>(c, Dl, B, group); break;
+            case VRT_MEDIUM_GAUSSIAN: march_group<VRT_MEDIUM_GAUSSIAN>(c, Dl, B, group); break;
+            default: march_group<VRT_MEDIUM_GRID>(c, Dl, B, group); break;
+            }
+            idle = 0;
+            continue;
+        }
+        // nothing to do: leave once idle long enough (all waves then leave)
+        ++idle;
+        if (idle > kIdlePolls && (idle % 8 == 0 || idle == kIdlePolls + 1)) {
+            const bool stop =
+                __hip_atomic_load(&mb->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+            const bool live =
+                __hip_atomic_load(&mb->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+            if (stop || !live || idle > kLingerPolls) {
+                if (c.lane == 0)
+                    __hip_atomic_store(&dc->exiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        // back off: the tail is one address polled by every idle wave
+        for (uint32_t q = 0; q < min(idle, 16u); ++q) __builtin_amdgcn_s_sleep(127);
     }
 }
 
@@ -261,7 +517,7 @@ struct HostJob {
     int error = 0;
     uint64_t steps = 0;
     double t_submit = 0, t_admit = 0, t_start = 0, t_retired = 0, t_done = 0;
-    hipEvent_t ev = nullptr;
+    hsa_signal_t sig{0};  // completion of the job's input or output copies
 };
 
 // First-fit allocator over [0, size) in 256-byte units.
@@ -325,26 +581,32 @@ struct vrt_server_s {
     size_t budget = 0;
     char *pool = nullptr;
     Pool alloc;
-    JobDesc *table = nullptr;
-    JobCtl *ctl = nullptr;
-    uint32_t *first_open = nullptr;
-    ServeCtl *sc = nullptr;         // pinned
-    DoneRec *done = nullptr;        // pinned
-    unsigned char *stage = nullptr; // pinned: descriptor + claim record per slot
-    hipStream_t copy_s = nullptr, run_s = nullptr;
+    JobDesc *hdesc = nullptr;  // pinned, coherent
+    Mailbox *mb = nullptr;     // pinned, coherent
+    DoneRec *done = nullptr;   // pinned, coherent
+    JobDesc *table = nullptr;  // device
+    JobCtl *ctl = nullptr;     // device
+    DevCtl *dc = nullptr;      // device
+    std::vector<char> slot_busy;
+    bool hsa_up = false;
+    hsa_agent_t gpu{0}, cpu{0};
+    std::vector<hsa_signal_t> free_sigs;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
     hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    hipEvent_t ev_run = nullptr;
+    hipGraphExec_t exec = nullptr;
     bool running = false;
-    uint32_t futile = 0;  // kernel runs since a job last retired
     uint32_t blocks = 0;
+    uint32_t futile = 0;  // kernel runs since a job last retired
     std::mutex mu;
     std::condition_variable cv_submit, cv_done;
-    std::deque<HostJob *> queued, staged;
+    std::deque<HostJob *> queued, staging;
     std::vector<HostJob *> live, copying;
     std::unordered_map<uint64_t, HostJob *> jobs;
+    std::map<std::vector<uint64_t>, uint32_t> groups;  // (medium, trace parameters) -> group id
     uint32_t next_seq = 0;
-    uint32_t in_flight = 0;  // admitted and not done
+    uint32_t admitted = 0;  // admitted and not retired (the mailbox's live)
+    uint32_t published = 0; // jobs [0, published) staged and announced
     bool quit = false;
     int fatal = 0;
     std::string fatal_msg;
@@ -357,20 +619,61 @@ struct vrt_server_s {
     }
 };
 
-static const int kStageBytes = (int)(kDescBytes + sizeof(JobCtl));
+static void set_fatal(vrt_server_t s, int code, const std::string &msg) {
+    if (!s->fatal) {
+        s->fatal = code;
+        s->fatal_msg = msg;
+    }
+}
 
-// Issue a job's input copies and its descriptor (scheduler thread, mu held).
-static hipError_t stage_job(vrt_server_t s, HostJob *J) {
-    const size_t n = J->n;
+static bool get_signal(vrt_server_t s, hsa_signal_value_t v, hsa_signal_t *out) {
+    if (!s->free_sigs.empty()) {
+        *out = s->free_sigs.back();
+        s->free_sigs.pop_back();
+        hsa_signal_store_screlease(*out, v);
+        return true;
+    }
+    return hsa_signal_create(v, 0, nullptr, out) == HSA_STATUS_SUCCESS;
+}
+
+static void put_signal(vrt_server_t s, hsa_signal_t &sg) {
+    if (sg.handle) s->free_sigs.push_back(sg);
+    sg.handle = 0;
+}
+
+// Copy engine transfer of `bytes` (the copy decrements `sig` when done).
+static bool dma(vrt_server_t s, void *dst, bool dst_dev, const void *src, size_t bytes,
+                hsa_signal_t sig) {
+    return hsa_amd_memory_async_copy(dst, dst_dev ? s->gpu : s->cpu, src,
+                                     dst_dev ? s->cpu : s->gpu, bytes, 0, nullptr,
+                                     sig) == HSA_STATUS_SUCCESS;
+}
+
+// Device arrays of a job in the pool: 12 float arrays, then 5 uint32 arrays.
+static void job_arrays(vrt_server_t s, const HostJob *J, float **f, uint32_t **u) {
     char *base = s->pool + J->off;
-    float *f = (float *)base;
-    uint32_t *u = (uint32_t *)(base + 12 * n * sizeof(float));
+    *f = (float *)base;
+    *u = (uint32_t *)(base + 12 * J->n * sizeof(float));
+}
+
+// Issue a job's input copies (scheduler thread, mu held).
+static bool stage_job(vrt_server_t s, HostJob *J) {
+    float *f;
+    uint32_t *u;
+    job_arrays(s, J, &f, &u);
     const void *in[6] = {J->host.px, J->host.py, J->host.pz, J->host.dx, J->host.dy, J->host.dz};
-    hipError_t e = hipSuccess;
-    for (int a = 0; a < 6 && e == hipSuccess; ++a)
-        e = hipMemcpyAsync(f + a * n, in[a], n * sizeof(float), hipMemcpyHostToDevice, s->copy_s);
-    if (e != hipSuccess) return e;
-    const uint32_t slot = J->seq % kSlots;
+    if (!get_signal(s, 6, &J->sig)) return false;
+    for (int a = 0; a < 6; ++a)
+        if (!dma(s, f + a * J->n, true, in[a], J->n * sizeof(float), J->sig)) return false;
+    return true;
+}
+
+// Write the descriptor of a staged job and announce it to the kernel.
+static void publish_job(vrt_server_t s, HostJob *J) {
+    const size_t n = J->n;
+    float *f;
+    uint32_t *u;
+    job_arrays(s, J, &f, &u);
     JobDesc d{};
     vrt_medium_t m = J->med;
     d.m = m->dev;
@@ -388,41 +691,39 @@ static hipError_t stage_job(vrt_server_t s, HostJob *J) {
                           u, u + n, u + 2 * n, u + 3 * n, u + 4 * n};
     d.n = (uint32_t)n;
     d.kind = m->dev.kind;
+    {
+        std::vector<uint64_t> key(8);
+        key[0] = (uint64_t)(uintptr_t)m;
+        const double pv[6] = {J->p.dL0, (double)J->p.max_steps, J->p.eps_tan, J->p.crit_rad,
+                              J->p.tie_eps, J->p.exit_plane_z};
+        for (int i = 0; i < 6; ++i) memcpy(&key[1 + i], &pv[i], 8);
+        auto it = s->groups.find(key);
+        if (it == s->groups.end()) it = s->groups.emplace(key, (uint32_t)s->groups.size()).first;
+        d.group = it->second;
+    }
     d.dL0 = (float)J->p.dL0;
     d.eps_tan = (float)J->p.eps_tan;
     d.mrg = fmaxf(2e-6f, 4.0f * (float)J->p.tie_eps);
     d.crit = (float)J->p.crit_rad;
-    JobCtl c{};
-    c.claim = (unsigned long long)J->seq << 32;
-    c.left = (uint32_t)n;
-    unsigned char *st = s->stage + (size_t)slot * kStageBytes;
-    memcpy(st, &d, sizeof d);
-    memcpy(st + kDescBytes, &c, sizeof c);
-    e = hipMemcpyAsync(s->table + slot, st, sizeof(JobDesc), hipMemcpyHostToDevice, s->copy_s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(s->ctl + slot, st + kDescBytes, sizeof(JobCtl), hipMemcpyHostToDevice,
-                           s->copy_s);
-    if (e == hipSuccess) e = hipEventRecord(J->ev, s->copy_s);
-    return e;
+    memcpy((void *)(s->hdesc + J->seq % kSlots), &d, sizeof d);
+    s->published = J->seq + 1;
+    __atomic_store_n(&s->mb->htail, s->published, __ATOMIC_RELEASE);
 }
 
-static hipError_t fetch_job(vrt_server_t s, HostJob *J) {
-    const size_t n = J->n;
-    char *base = s->pool + J->off;
-    float *f = (float *)base;
-    uint32_t *u = (uint32_t *)(base + 12 * n * sizeof(float));
+// Issue a retired job's output copies.
+static bool fetch_job(vrt_server_t s, HostJob *J) {
+    float *f;
+    uint32_t *u;
+    job_arrays(s, J, &f, &u);
     void *outf[6] = {J->host.ox, J->host.oy, J->host.oz, J->host.odx, J->host.ody, J->host.odz};
-    uint32_t *outu[5] = {J->host.status, J->host.steps, J->host.n_tir, J->host.n_btir,
-                         J->host.flags};
-    hipError_t e = hipSuccess;
-    for (int a = 0; a < 6 && e == hipSuccess; ++a)
-        e = hipMemcpyAsync(outf[a], f + (6 + a) * n, n * sizeof(float), hipMemcpyDeviceToHost,
-                           s->copy_s);
-    for (int a = 0; a < 5 && e == hipSuccess; ++a)
-        e = hipMemcpyAsync(outu[a], u + a * n, n * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                           s->copy_s);
-    if (e == hipSuccess) e = hipEventRecord(J->ev, s->copy_s);
-    return e;
+    void *outu[5] = {J->host.status, J->host.steps, J->host.n_tir, J->host.n_btir,
+                     J->host.flags};
+    if (!get_signal(s, 11, &J->sig)) return false;
+    for (int a = 0; a < 6; ++a)
+        if (!dma(s, outf[a], false, f + (6 + a) * J->n, J->n * sizeof(float), J->sig)) return false;
+    for (int a = 0; a < 5; ++a)
+        if (!dma(s, outu[a], false, u + a * J->n, J->n * sizeof(uint32_t), J->sig)) return false;
+    return true;
 }
 
 static void finish_job(vrt_server_t s, HostJob *J, int err) {
@@ -430,63 +731,85 @@ static void finish_job(vrt_server_t s, HostJob *J, int err) {
     J->error = err;
     J->t_done = s->now();
     s->alloc.release(J->off, J->bytes);
-    s->in_flight--;
+    s->slot_busy[J->seq % kSlots] = 0;
     J->med->jobs--;
     s->st.jobs_done++;
     s->st.rays_done += J->n;
     s->st.ray_steps_done += J->steps;
+    s->st.pool_bytes = s->alloc.used();
 }
+
+static void set_live(vrt_server_t s) { __atomic_store_n(&s->mb->live, s->admitted, __ATOMIC_RELEASE); }
 
 // One pass of the scheduler (mu held).  Returns true if anything moved.
 static bool schedule_once(vrt_server_t s) {
     bool moved = false;
     hipError_t e = hipSuccess;
-    // 1. admission in submission order: pool space and a job slot
-    while (!s->queued.empty() && s->in_flight < kSlots - 1) {
+    // 1. admission in submission order: pool space and the job's slot free;
+    //    the input copies start at once
+    while (!s->queued.empty()) {
         HostJob *J = s->queued.front();
+        if (s->slot_busy[J->seq % kSlots]) break;
         if (!s->alloc.alloc(J->bytes, &J->off)) break;
         s->queued.pop_front();
-        s->in_flight++;
+        s->slot_busy[J->seq % kSlots] = 1;
         s->st.pool_bytes = s->alloc.used();
         s->st.pool_peak_bytes = s->alloc.peak();
-        J->state = VRT_JOB_STAGED;
         J->t_admit = s->now();
-        if ((e = stage_job(s, J)) != hipSuccess) goto fail;
-        s->staged.push_back(J);
+        J->state = VRT_JOB_RUNNING;
+        s->admitted++;
+        set_live(s);
+        if (!stage_job(s, J)) {
+            set_fatal(s, VRT_EHIP, "server: input copy could not be issued");
+            return false;
+        }
+        s->staging.push_back(J);
         moved = true;
     }
-    // 2. publish, in order, the jobs whose inputs have arrived
-    while (!s->staged.empty()) {
-        HostJob *J = s->staged.front();
-        e = hipEventQuery(J->ev);
-        if (e == hipErrorNotReady) break;
-        if (e != hipSuccess) goto fail;
-        s->staged.pop_front();
-        J->state = VRT_JOB_RUNNING;
+    // 2. staged jobs are announced in order, once their inputs are in the pool
+    while (!s->staging.empty()) {
+        HostJob *J = s->staging.front();
+        const hsa_signal_value_t v = hsa_signal_load_scacquire(J->sig);
+        if (v < 0) {
+            set_fatal(s, VRT_EHIP, "server: input copy failed");
+            return false;
+        }
+        if (v > 0) break;
+        put_signal(s, J->sig);
+        publish_job(s, J);
         J->t_start = s->now();
-        std::atomic_thread_fence(std::memory_order_seq_cst);
-        __atomic_store_n(&s->sc->tail, J->seq + 1, __ATOMIC_RELEASE);
+        s->staging.pop_front();
         s->live.push_back(J);
         moved = true;
     }
-    // 3. the persistent kernel: relaunch when it idled out and work is live
+    // 3. the persistent kernel runs while jobs are admitted
     if (s->running) {
-        e = hipEventQuery(s->ev_run);
-        if (e == hipSuccess) s->running = false;
-        else if (e != hipErrorNotReady) goto fail;
+        e = hipEventQuery(s->ev);
+        if (e == hipSuccess) {
+            s->running = false;
+        } else if (e != hipErrorNotReady) {
+            goto fail;
+        }
     }
-    if (!s->running && !s->live.empty()) {
+    if (!s->running && s->admitted > 0) {
         // a run that retires nothing while jobs are live can only repeat: stop
-        if (++s->futile > 2000) {
-            s->fatal = VRT_EHIP;
-            s->fatal_msg = "server: published jobs make no progress";
+        if (++s->futile > 16) {
+            set_fatal(s, VRT_EHIP, "server: published jobs make no progress");
             return false;
         }
-        if ((e = hipGraphLaunch(s->gexec, s->run_s)) != hipSuccess) goto fail;
-        if ((e = hipEventRecord(s->ev_run, s->run_s)) != hipSuccess) goto fail;
+        // the previous run has ended: clear its exit flag (no wave reads it now)
+        if ((e = hipMemsetAsync(&s->dc->exiting, 0, sizeof(uint32_t), s->stream)) != hipSuccess)
+            goto fail;
+        if ((e = hipGraphLaunch(s->exec, s->stream)) != hipSuccess) goto fail;
+        if ((e = hipEventRecord(s->ev, s->stream)) != hipSuccess) goto fail;
         s->running = true;
         s->st.kernel_launches++;
+        s->st.lanes = s->blocks * 256;
         moved = true;
+    }
+    if (__atomic_load_n(&s->mb->lost, __ATOMIC_ACQUIRE)) {
+        set_fatal(s, VRT_EHIP, "server: a ray claim met a reused job slot; rays were lost");
+        return false;
     }
     // 4. retired jobs: copy their outputs back
     for (size_t i = 0; i < s->live.size();) {
@@ -497,7 +820,12 @@ static bool schedule_once(vrt_server_t s) {
             J->t_retired = s->now();
             J->state = VRT_JOB_COPYING;
             s->futile = 0;
-            if ((e = fetch_job(s, J)) != hipSuccess) goto fail;
+            s->admitted--;
+            set_live(s);
+            if (!fetch_job(s, J)) {
+                set_fatal(s, VRT_EHIP, "server: output copy could not be issued");
+                return false;
+            }
             s->copying.push_back(J);
             s->live[i] = s->live.back();
             s->live.pop_back();
@@ -509,12 +837,16 @@ static bool schedule_once(vrt_server_t s) {
     // 5. outputs in host memory: done
     for (size_t i = 0; i < s->copying.size();) {
         HostJob *J = s->copying[i];
-        e = hipEventQuery(J->ev);
-        if (e == hipErrorNotReady) {
+        const hsa_signal_value_t v = hsa_signal_load_scacquire(J->sig);
+        if (v < 0) {
+            set_fatal(s, VRT_EHIP, "server: output copy failed");
+            return false;
+        }
+        if (v > 0) {
             ++i;
             continue;
         }
-        if (e != hipSuccess) goto fail;
+        put_signal(s, J->sig);
         finish_job(s, J, 0);
         s->copying[i] = s->copying.back();
         s->copying.pop_back();
@@ -523,28 +855,26 @@ static bool schedule_once(vrt_server_t s) {
     if (moved) s->cv_done.notify_all();
     return moved;
 fail:
-    s->fatal = e == hipErrorOutOfMemory ? VRT_ENOMEM : VRT_EHIP;
-    s->fatal_msg = std::string("server: ") + hipGetErrorString(e);
+    set_fatal(s, e == hipErrorOutOfMemory ? VRT_ENOMEM : VRT_EHIP,
+              std::string("server: ") + hipGetErrorString(e));
     return false;
 }
 
+static void fail_job(vrt_server_t s, HostJob *J) {
+    J->state = VRT_JOB_DONE;
+    J->error = s->fatal;
+    J->med->jobs--;
+}
+
+// After a fatal error: every job not done fails.  Jobs whose copies may still
+// be in flight keep their pool space (the pool is not reused after this).
 static void fail_all(vrt_server_t s) {
-    for (auto *v : {&s->queued, &s->staged}) {
-        for (HostJob *J : *v) {
-            if (J->state != VRT_JOB_QUEUED) s->in_flight--;
-            J->state = VRT_JOB_DONE;
-            J->error = s->fatal;
-            J->med->jobs--;
-        }
+    for (auto *v : {&s->queued, &s->staging}) {
+        for (HostJob *J : *v) fail_job(s, J);
         v->clear();
     }
     for (auto *v : {&s->live, &s->copying}) {
-        for (HostJob *J : *v) {
-            J->state = VRT_JOB_DONE;
-            J->error = s->fatal;
-            J->med->jobs--;
-            s->in_flight--;
-        }
+        for (HostJob *J : *v) fail_job(s, J);
         v->clear();
     }
     s->cv_done.notify_all();
@@ -558,7 +888,7 @@ static void scheduler(vrt_server_t s) {
             fail_all(s);
             break;
         }
-        const bool busy = !s->queued.empty() || !s->staged.empty() || !s->live.empty() ||
+        const bool busy = !s->queued.empty() || !s->staging.empty() || !s->live.empty() ||
                           !s->copying.empty();
         if (s->quit && !busy) break;
         const bool moved = schedule_once(s);
@@ -570,29 +900,65 @@ static void scheduler(vrt_server_t s) {
     }
 }
 
+// Wait (bounded) for copies a failed server may still have in flight.
+static void drain_signals(vrt_server_t s) {
+    for (auto &kv : s->jobs) {
+        HostJob *J = kv.second;
+        if (J->sig.handle) {
+            (void)hsa_signal_wait_scacquire(J->sig, HSA_SIGNAL_CONDITION_LT, 1, 10000000000ull,
+                                            HSA_WAIT_STATE_BLOCKED);
+            (void)hsa_signal_destroy(J->sig);
+            J->sig.handle = 0;
+        }
+    }
+}
+
 static int server_free(vrt_server_t s) {
     int rc = VRT_OK;
-    if (s->run_s && hipStreamSynchronize(s->run_s) != hipSuccess) rc = VRT_EHIP;
-    if (s->copy_s && hipStreamSynchronize(s->copy_s) != hipSuccess) rc = VRT_EHIP;
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->mb) __atomic_store_n(&s->mb->stop, 1u, __ATOMIC_RELEASE);
+    if (s->stream && hipStreamSynchronize(s->stream) != hipSuccess) rc = VRT_EHIP;
+    if (s->hsa_up) drain_signals(s);
+    for (auto &sg : s->free_sigs) (void)hsa_signal_destroy(sg);
+    s->free_sigs.clear();
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
-    if (s->ev_run) (void)hipEventDestroy(s->ev_run);
-    for (auto &kv : s->jobs) {
-        if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
-        delete kv.second;
-    }
-    if (s->run_s) (void)hipStreamDestroy(s->run_s);
-    if (s->copy_s) (void)hipStreamDestroy(s->copy_s);
+    if (s->ev) (void)hipEventDestroy(s->ev);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    for (auto &kv : s->jobs) delete kv.second;
     if (s->pool) (void)hipFree(s->pool);
     if (s->table) (void)hipFree(s->table);
     if (s->ctl) (void)hipFree(s->ctl);
-    if (s->first_open) (void)hipFree(s->first_open);
-    if (s->sc) (void)hipHostFree(s->sc);
+    if (s->dc) (void)hipFree(s->dc);
+    if (s->hdesc) (void)hipHostFree(s->hdesc);
+    if (s->mb) (void)hipHostFree(s->mb);
     if (s->done) (void)hipHostFree(s->done);
-    if (s->stage) (void)hipHostFree(s->stage);
+    if (s->hsa_up) (void)hsa_shut_down();
     if (s->ctx) s->ctx->n_servers--;
     delete s;
     return rc;
+}
+
+// The HSA agent owning an allocation (GPU for device memory, CPU for pinned
+// host memory), and whether [p, p + bytes) lies inside that allocation.
+static bool owner_of(const void *p, size_t bytes, hsa_agent_t *agent) {
+    hsa_amd_pointer_info_t info;
+    memset(&info, 0, sizeof info);
+    info.size = sizeof info;
+    if (hsa_amd_pointer_info(p, &info, nullptr, nullptr, nullptr) != HSA_STATUS_SUCCESS)
+        return false;
+    if (info.type == HSA_EXT_POINTER_TYPE_UNKNOWN) return false;
+    const char *base = (const char *)info.hostBaseAddress;
+    if (!base) base = (const char *)info.agentBaseAddress;
+    if (!base || (const char *)p < base || (const char *)p + bytes > base + info.sizeInBytes)
+        return false;
+    *agent = info.agentOwner;
+    return true;
+}
+
+static bool is_cpu(hsa_agent_t a) {
+    hsa_device_type_t t;
+    return hsa_agent_get_info(a, HSA_AGENT_INFO_DEVICE, &t) == HSA_STATUS_SUCCESS &&
+           t == HSA_DEVICE_TYPE_CPU;
 }
 
 extern "C" int vrt_server_create(vrt_context_t ctx, size_t hbm_budget, int max_lanes,
@@ -607,56 +973,61 @@ extern "C" int vrt_server_create(vrt_context_t ctx, size_t hbm_budget, int max_l
     ctx->n_servers++;
     s->budget = hbm_budget & ~(size_t)255;
     s->alloc.reset(s->budget);
+    s->slot_busy.assign(kSlots, 0);
     s->t0 = std::chrono::steady_clock::now();
     hipError_t e;
-#define SV_TRY(call, what)                    \
-    if ((e = (call)) != hipSuccess) {         \
+#define SV_TRY(call, what)                            \
+    if ((e = (call)) != hipSuccess) {                 \
         rc = fail_hip(e, "vrt_server_create: " what); \
-        server_free(s);                       \
-        return rc;                            \
+        server_free(s);                               \
+        return rc;                                    \
     }
+#define SV_FAIL(what)                                            \
+    do {                                                         \
+        rc = fail(VRT_EHIP, "vrt_server_create: %s", what);      \
+        server_free(s);                                          \
+        return rc;                                               \
+    } while (0)
     SV_TRY(hipMalloc((void **)&s->pool, s->budget), "pool");
     SV_TRY(hipMalloc((void **)&s->table, sizeof(JobDesc) * kSlots), "job table");
     SV_TRY(hipMalloc((void **)&s->ctl, sizeof(JobCtl) * kSlots), "job counters");
-    SV_TRY(hipMalloc((void **)&s->first_open, 256), "first-open word");
-    SV_TRY(hipHostMalloc((void **)&s->sc, sizeof(ServeCtl), hipHostMallocCoherent), "control words");
+    SV_TRY(hipMalloc((void **)&s->dc, sizeof(DevCtl)), "control words");
+    SV_TRY(hipHostMalloc((void **)&s->hdesc, sizeof(JobDesc) * kSlots, hipHostMallocCoherent),
+           "descriptors");
+    SV_TRY(hipHostMalloc((void **)&s->mb, sizeof(Mailbox), hipHostMallocCoherent), "mailbox");
     SV_TRY(hipHostMalloc((void **)&s->done, sizeof(DoneRec) * kSlots, hipHostMallocCoherent),
            "done records");
-    SV_TRY(hipHostMalloc((void **)&s->stage, (size_t)kStageBytes * kSlots, hipHostMallocDefault),
-           "staging");
-    memset(s->sc, 0, sizeof(ServeCtl));
-    memset(s->done, 0, sizeof(DoneRec) * kSlots);
-    SV_TRY(hipStreamCreateWithFlags(&s->copy_s, hipStreamNonBlocking), "copy stream");
-    SV_TRY(hipStreamCreateWithFlags(&s->run_s, hipStreamNonBlocking), "run stream");
-    SV_TRY(hipEventCreateWithFlags(&s->ev_run, hipEventDisableTiming), "event");
+    memset((void *)s->hdesc, 0, sizeof(JobDesc) * kSlots);
+    memset((void *)s->mb, 0, sizeof(Mailbox));
+    memset((void *)s->done, 0, sizeof(DoneRec) * kSlots);
+    if (hsa_init() != HSA_STATUS_SUCCESS) SV_FAIL("hsa_init");
+    s->hsa_up = true;
+    if (!owner_of(s->pool, s->budget, &s->gpu) || is_cpu(s->gpu)) SV_FAIL("pool agent");
+    if (!owner_of(s->mb, sizeof(Mailbox), &s->cpu) || !is_cpu(s->cpu)) SV_FAIL("host agent");
+    SV_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "stream");
+    SV_TRY(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming), "event");
     // claim words of empty slots name no job (sequence 0xffffffff)
     {
         std::vector<JobCtl> c0(kSlots);
         for (auto &c : c0) c.claim = 0xffffffffull << 32;
         SV_TRY(hipMemcpy(s->ctl, c0.data(), sizeof(JobCtl) * kSlots, hipMemcpyHostToDevice),
                "counter init");
-        std::vector<JobDesc> d0(1);
-        for (uint32_t k = 0; k < kSlots; ++k)
-            SV_TRY(hipMemcpy(s->table + k, d0.data(), sizeof(JobDesc), hipMemcpyHostToDevice),
-                   "table init");
-        uint32_t z[64] = {0};
-        SV_TRY(hipMemcpy(s->first_open, z, 256, hipMemcpyHostToDevice), "first-open init");
+        SV_TRY(hipMemset(s->table, 0, sizeof(JobDesc) * kSlots), "table init");
+        SV_TRY(hipMemset(s->dc, 0, sizeof(DevCtl)), "control init");
     }
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, serve_kernel, 256, 0) != hipSuccess ||
-        nb <= 0)
-        nb = 1;
-    s->blocks = (uint32_t)ctx->num_cu * (uint32_t)nb;
-    if (max_lanes > 0) s->blocks = std::min(s->blocks, (uint32_t)((max_lanes + 255) / 256));
+    int occ = 0;
+    SV_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, serve_kernel, 256, 0), "occupancy");
+    occ = std::max(occ, 1);
+    s->blocks = (uint32_t)ctx->num_cu * (uint32_t)occ;
+    if (max_lanes > 0) s->blocks = std::min(s->blocks, std::max(1u, (uint32_t)max_lanes / 256u));
+    SV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal), "capture");
+    hipLaunchKernelGGL(serve_kernel, dim3(s->blocks), dim3(256), 0, s->stream, s->hdesc, s->table,
+                       s->ctl, s->dc, s->mb, s->done);
+    SV_TRY(hipStreamEndCapture(s->stream, &s->graph), "capture");
+    SV_TRY(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0), "graph");
     s->st.job_slots = kSlots;
-    s->st.lanes = s->blocks * 256;
-    // capture the persistent kernel's launch once; relaunches replay it
-    SV_TRY(hipStreamBeginCapture(s->run_s, hipStreamCaptureModeThreadLocal), "capture");
-    hipLaunchKernelGGL(serve_kernel, dim3(s->blocks), dim3(256), 0, s->run_s, s->table, s->ctl,
-                       s->sc, s->done, s->first_open);
-    SV_TRY(hipStreamEndCapture(s->run_s, &s->graph), "capture end");
-    SV_TRY(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0), "graph instantiate");
 #undef SV_TRY
+#undef SV_FAIL
     s->th = std::thread(scheduler, s);
     *out = s;
     return VRT_OK;
@@ -683,17 +1054,20 @@ extern "C" int vrt_server_submit(vrt_server_t s, vrt_medium_t m, const vrt_trace
                           host_rays->oz, host_rays->odx, host_rays->ody, host_rays->odz,
                           host_rays->status, host_rays->steps, host_rays->n_tir,
                           host_rays->n_btir, host_rays->flags};
-    for (const void *q : ptrs)
-        if (!q || ((uintptr_t)q & 3)) return fail(VRT_EINVAL, "vrt_server_submit: NULL or misaligned array");
+    for (const void *q : ptrs) {
+        if (!q || ((uintptr_t)q & 3))
+            return fail(VRT_EINVAL, "vrt_server_submit: NULL or misaligned array");
+        hsa_agent_t a;
+        if (!owner_of(q, n_rays * 4, &a) || !is_cpu(a))
+            return fail(VRT_EINVAL,
+                        "vrt_server_submit: every array must lie in pinned host memory "
+                        "(hipHostMalloc)");
+    }
     const size_t bytes = ((n_rays * kRayBytes + 255) & ~(size_t)255) + 256;
     if (bytes > s->budget)
         return fail(VRT_EINVAL, "vrt_server_submit: %zu rays need %zu bytes, the pool has %zu",
                     n_rays, bytes, s->budget);
     HostJob *J = new HostJob();
-    if (hipEventCreateWithFlags(&J->ev, hipEventDisableTiming) != hipSuccess) {
-        delete J;
-        return fail(VRT_EHIP, "vrt_server_submit: event");
-    }
     J->med = m;
     J->p = *p;
     J->host = *host_rays;
@@ -702,7 +1076,6 @@ extern "C" int vrt_server_submit(vrt_server_t s, vrt_medium_t m, const vrt_trace
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->fatal) {
-            (void)hipEventDestroy(J->ev);
             delete J;
             return fail(s->fatal, "%s", s->fatal_msg.c_str());
         }
@@ -773,8 +1146,7 @@ extern "C" int vrt_server_destroy(vrt_server_t s) {
     }
     s->cv_submit.notify_all();
     if (s->th.joinable()) s->th.join();
-    // every job is done: tell the kernel to leave, and wait for it
-    __atomic_store_n(&s->sc->stop, 1u, __ATOMIC_RELEASE);
+    // every job is done (or failed): server_free tells the kernel to leave and waits
     const int fatal = s->fatal;
     const std::string msg = s->fatal_msg;
     const int rc = server_free(s);

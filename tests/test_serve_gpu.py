@@ -3,7 +3,8 @@ several device-resident media, admitted by a device pool budget, marched by
 one persistent kernel.  Checks: every ray of a job in the mix equals the same
 job served alone (bitwise), served results meet the parity bar against the
 FP64 oracle, admission under a small pool, relaunch of the idled-out kernel,
-and the API's refusals."""
+a lane cap, and the API's refusals (including host arrays that are not
+pinned)."""
 import time
 
 import numpy as np
@@ -187,6 +188,10 @@ def test_server_refusals(vrt, ctx, media):
         assert "pool" in vrt.vrt_last_error()
         with pytest.raises(vrt.VrtError):
             srv.query(123456)
+        pageable = vrt.HostRays(P0, d0, pin=False)  # the copy engines need pinned memory
+        with pytest.raises(vrt.VrtError):
+            srv.submit(meds[0], pageable, prm)
+        assert "pinned" in vrt.vrt_last_error()
         job = srv.submit(meds[0], h, prm)
         srv.wait(job, 60.0)
         assert srv.query(job)["state"] == "DONE"
