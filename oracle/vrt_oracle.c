@@ -176,6 +176,61 @@ static void medium_eval(const orc_medium *m, const double P[3], double *n, doubl
     case ORC_GRID:
         grid_eval(m, P, n, g);
         return;
+    case ORC_SPHERICAL: {
+        /* Sec. V, Eq. (26): n = a0 + a1 G1 + a2 G2 + a3 G3 in spherical
+         * coordinates (r, theta, phi) about the centre c, theta measured from
+         * the z axis:  G1 = 0.3 (r^2 - 1),  G2 = r cos(5 theta),
+         * G3 = r^2 sin^2(theta) cos(2 phi).  The gradient is
+         * dn/dr r^ + (1/r) dn/dtheta theta^ + 1/(r sin theta) dn/dphi phi^.
+         * At r = 0 the direction of G2's gradient is undefined (a cusp): the
+         * gradient is returned as NaN there, which the march takes as case (ii). */
+        double a0 = p[0], a1 = p[1], a2 = p[2], a3 = p[3];
+        double x = P[0] - p[4], y = P[1] - p[5], z = P[2] - p[6];
+        double r = sqrt(x * x + y * y + z * z);
+        if (r == 0.0) {
+            *n = a0 - 0.3 * a1;
+            g[0] = g[1] = g[2] = NAN;
+            return;
+        }
+        double th = acos(fmax(-1.0, fmin(1.0, z / r)));
+        double ph = atan2(y, x);
+        double st = sin(th), ct = cos(th), sp = sin(ph), cp = cos(ph);
+        double G1 = 0.3 * (r * r - 1.0);
+        double G2 = r * cos(5.0 * th);
+        double G3 = r * r * st * st * cos(2.0 * ph);
+        *n = a0 + a1 * G1 + a2 * G2 + a3 * G3;
+        /* components along r^, theta^, phi^ */
+        double dr = a1 * 0.6 * r + a2 * cos(5.0 * th) + a3 * 2.0 * r * st * st * cos(2.0 * ph);
+        double dt = a2 * (-5.0 * sin(5.0 * th)) + a3 * 2.0 * r * st * ct * cos(2.0 * ph);
+        double dp = a3 * (-2.0 * r * st * sin(2.0 * ph));
+        double er[3] = {st * cp, st * sp, ct};
+        double et[3] = {ct * cp, ct * sp, -st};
+        double ep[3] = {-sp, cp, 0.0};
+        for (int a = 0; a < 3; ++a) g[a] = dr * er[a] + dt * et[a] + dp * ep[a];
+        return;
+    }
+    case ORC_N2P: {
+        /* Sec. VI, Eq. (27): n = [1 + ((R^2 - (rho/2)^2) / F^2)^beta]^gamma inside
+         * the lens (rho = distance from the z axis); the lens volume
+         * (0 <= rho <= R, -L <= z <= 0) is the enclosing cylinder and n = 1 the
+         * surroundings.  dn/drho = gamma [1 + w^beta]^(gamma - 1) beta w^(beta - 1)
+         * dw/drho with w = (R^2 - rho^2/4) / F^2, dw/drho = -rho / (2 F^2). */
+        double R = p[0], F = p[1], be = p[2], ga = p[3];
+        double x = P[0], y = P[1];
+        double rho = sqrt(x * x + y * y);
+        double w = (R * R - (rho / 2.0) * (rho / 2.0)) / (F * F);
+        double u = 1.0 + pow(w, be);
+        *n = pow(u, ga);
+        double dndrho = ga * pow(u, ga - 1.0) * be * pow(w, be - 1.0) * (-rho / (2.0 * F * F));
+        if (rho == 0.0) {
+            g[0] = g[1] = g[2] = 0.0;
+        } else {
+            g[0] = dndrho * x / rho;
+            g[1] = dndrho * y / rho;
+            g[2] = 0.0;
+        }
+        return;
+    }
     default:
         *n = NAN;
         g[0] = g[1] = g[2] = NAN;
@@ -667,7 +722,12 @@ static int check_medium(const orc_medium *m, const orc_params *q) {
     if (!(m->n_amb > 0.0)) return -1;
     if (m->kind == ORC_GRID) {
         if (!m->grid || m->nx < 2 || m->ny < 2 || m->nz < 2) return -1;
-    } else if (m->kind < 0 || m->kind > ORC_GRID || !m->params) {
+    } else if (m->kind < 0 || m->kind > ORC_N2P || !m->params) {
+        return -1;
+    } else if (m->kind == ORC_SPHERICAL && m->n_params != 7) {
+        return -1;
+    } else if (m->kind == ORC_N2P &&
+               (m->n_params != 4 || !(m->params[0] > 0.0) || !(m->params[1] > 0.0))) {
         return -1;
     }
     if (m->bkind < ORC_BOX || m->bkind > ORC_CYLINDER) return -1;

@@ -27,7 +27,9 @@ enum {
     ORC_LUNEBURG = 2,    /* params [R, cx, cy, cz]       n = sqrt(2 - r^2/R^2)    */
     ORC_FIBER = 3,       /* params [n_c, Delta, R, cx, cy]  Sec. IV, Eq. (21)     */
     ORC_GAUSSIAN = 4,    /* params [n0, K, (A, sigma, cx, cy, cz) x K]            */
-    ORC_GRID = 5         /* trilinear grid, node-central-difference gradient      */
+    ORC_GRID = 5,        /* trilinear grid, node-central-difference gradient      */
+    ORC_SPHERICAL = 6,   /* params [a0, a1, a2, a3, cx, cy, cz]  Sec. V, Eq. (26) */
+    ORC_N2P = 7          /* params [R, F, beta, gamma]  Sec. VI, Eq. (27), axis z */
 };
 
 /* boundary kinds (convex enclosing surface, Sec. II case (i)) */

@@ -12,7 +12,8 @@ them as float64).
 
 Media are plain dicts::
 
-    {"kind": "luneburg" | "gaussian" | "linear" | "homogeneous" | "fiber" | "grid",
+    {"kind": "luneburg" | "gaussian" | "linear" | "homogeneous" | "fiber" | "grid" |
+             "spherical" | "n2p",
      "params": float64 array (layout per kind, see ``MEDIUM_PARAM_LAYOUT``),
      "boundary": {"kind": "box" | "sphere" | "cylinder", "params": float64 array},
      "n_amb": float,
@@ -38,6 +39,8 @@ MEDIUM_PARAM_LAYOUT = {
     "fiber": "[n_c, Delta, R, cx, cy]       parabolic core about the z axis through (cx, cy)",
     "gaussian": "[n0, K, (A, sigma, cx, cy, cz) x K]",
     "grid": "[] (values in 'grid', nodes spanning grid_lo..grid_hi)",
+    "spherical": "[a0, a1, a2, a3, cx, cy, cz]  Sec. V, Eq. (26) about (cx, cy, cz)",
+    "n2p": "[R, F, beta, gamma]          Sec. VI, Eq. (27), axis z; lens = cylinder boundary",
 }
 BOUNDARY_PARAM_LAYOUT = {
     "box": "[lox, loy, loz, hix, hiy, hiz]",
@@ -220,6 +223,64 @@ def design_problem(N=64, n_side=512, seed_grid=4, seed_target=204, n0=1.5, jitte
 # ---------------------------------------------------------------------------
 # Served mix: a Poisson stream of trace jobs against resident media
 # ---------------------------------------------------------------------------
+# ---------------------------------------------------------------------------
+# Spherical freeform medium (Sec. V, Eq. (26)) and the N2P lens (Sec. VI)
+# ---------------------------------------------------------------------------
+def spherical_medium(a=(1.5, 1.0, -0.2, 0.3), center=(0.0, 0.0, 0.0)):
+    """n = a0 + a1 G1 + a2 G2 + a3 G3 inside the unit sphere about `center`
+    (r_max = 1), surroundings n = 1.  Default coefficients are the paper's."""
+    c = np.asarray(center, dtype=np.float64)
+    return {"kind": "spherical", "params": np.concatenate([np.asarray(a, dtype=np.float64), c]),
+            "boundary": {"kind": "sphere", "params": np.concatenate([c, [1.0]])},
+            "n_amb": 1.0}
+
+
+def sphere_aimed_rays(n_rays, seed, r_launch=1.5, r_target=0.8):
+    """Rays launched from the sphere of radius r_launch about the origin
+    towards a point drawn uniformly in the ball of radius r_target.
+
+    One draw u ~ U[0,1) of shape (n_rays, 5); row i belongs to ray i:
+    launch direction (cos t = 1 - 2 u0, phi = 2 pi u1), target radius
+    r_target u2^(1/3), target direction (1 - 2 u3, 2 pi u4).  Rounded to
+    float32.
+    """
+    rng = np.random.default_rng(seed)
+    u = rng.random((n_rays, 5))
+
+    def unit(ct, ph):
+        st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+        return np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=1)
+
+    P0 = r_launch * unit(1.0 - 2.0 * u[:, 0], 2.0 * math.pi * u[:, 1])
+    T = (r_target * np.cbrt(u[:, 2]))[:, None] * unit(1.0 - 2.0 * u[:, 3], 2.0 * math.pi * u[:, 4])
+    d0 = T - P0
+    d0 /= np.linalg.norm(d0, axis=1)[:, None]
+    return _f32(P0), _f32(d0)
+
+
+def n2p_lens(beta, gamma, L, R=1.0, F=2.0):
+    """Cylindrical N2P-GRIN lens of radius R, focal distance F and thickness L
+    occupying 0 <= rho <= R, -L <= z <= 0, in air."""
+    return {"kind": "n2p", "params": np.array([R, F, beta, gamma], dtype=np.float64),
+            "boundary": {"kind": "cylinder", "params": np.array([0.0, 0.0, R, -L, 0.0])},
+            "n_amb": 1.0}
+
+
+def n2p_heights(N=10, R=1.0, h_max=0.995):
+    """Ray heights of the design: N rays on the y axis, uniformly spaced,
+    excluding y = 0, the highest at h_max R:  y_i = h_max R i / N, i = 1..N."""
+    return h_max * R * np.arange(1, N + 1, dtype=np.float64) / N
+
+
+def n2p_rays(L, N=10, R=1.0, h_max=0.995, gap=0.1):
+    """Launch states of the design rays: parallel to the axis (+z), from
+    (0, y_i, -L - gap R) in the air before the lens."""
+    y = n2p_heights(N, R, h_max)
+    P0 = np.stack([np.zeros(N), y, np.full(N, -L - gap * R)], axis=1)
+    d0 = np.tile([0.0, 0.0, 1.0], (N, 1))
+    return P0, d0
+
+
 def served_media(grid_sizes=(128, 160, 192, 256)):
     """Eight media: four Gaussian-bump cubes (seeds 500..503) and four quantized
     grids (seeds 504..507) with the given edge sizes."""
