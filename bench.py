@@ -1,7 +1,8 @@
 #!/usr/bin/env python3
 """Benchmark of the constant-OPL vectorial ray march on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload freeform|grid|luneburg]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload freeform|grid|luneburg|served|n2p]
 
 A "step" of this benchmark is one pass of the whole hot path over one batch:
 one vrt_trace call that launches, enters, marches (medium evaluation, normal,
@@ -308,13 +309,105 @@ def served_bench(vrt, torch, args):
             "p99_speedup_vs_fp64": fp64["p99_ms"] / served["p99_ms"]}
 
 
+# ---------------------------------------------------------------------------
+# the paper's design example: N2P lens design loop (Sec. VI)
+# ---------------------------------------------------------------------------
+PEAK_FP64_TFLOPS = 78.6
+N2P_FLOPS_PER_STEP = 69  # index 19 (rho^2 3, w 4, two powers 2, u 1, gradient 9) + march 50
+
+
+def n2p_bench(vrt, torch, args, L=0.3, cpu_candidates=256):
+    """Successive refinement of the N2P lens of thickness 0.3 R, F = 2R
+    (the configuration of the paper's Fig. 6), 10 rays per candidate,
+    dL0 = 1e-4 R, a 33 x 33 candidate grid per level; each level is one
+    vrt_n2p_sweep launch, timed with HIP events on its stream."""
+    from paper_2606_22655_amd import design
+
+    ctx = vrt.Context(0)
+    stream = torch.cuda.current_stream()
+    spec = workloads.n2p_lens(1.0, 1.0, L)
+    y = workloads.n2p_heights()
+    P0, _ = workloads.n2p_rays(L)
+    prm = vrt.make_params({"dL0": 1e-4, "max_steps": 200000}, "fp64")
+    lens = vrt.Medium(ctx, spec)
+    per, steps, cands = [], [0], [0]
+
+    def score(bg):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rm, st = vrt.vrt_n2p_sweep(lens.handle, bg, y, P0[0, 2], prm, stream.cuda_stream,
+                                   want_steps=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per.append(e0.elapsed_time(e1))
+        steps[0] += int(st.sum())
+        cands[0] += len(bg)
+        print(f"[n2p] level {len(per)}: {len(bg)} candidates, {per[-1]:.1f} ms", file=sys.stderr,
+              flush=True)
+        return rm
+
+    design.refine(score, levels=1)  # warmup (one level)
+    per.clear()
+    steps[0] = cands[0] = 0
+    t0 = time.perf_counter()
+    b, g, e, hist = design.refine(score)
+    wall = time.perf_counter() - t0
+    lens.close()
+    kernel_s = sum(per) / 1e3
+    value = steps[0] / kernel_s
+    achieved = N2P_FLOPS_PER_STEP * steps[0] / kernel_s / 1e12
+    out = {"metric": METRIC, "value": value, "unit": "ray-steps/s", "n_gpus": 1,
+           "steps": len(per), "warmup": 1, "ms_per_step": round(float(np.mean(per)), 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"N2P lens design loop (Sec. VI): L = {L} R, F = 2 R, 10 rays "
+                                  "at y_i = 0.995 R i / 10, dL0 = 1e-4 R, 33 x 33 (beta, gamma) "
+                                  "grid per refinement level, plain FP64 march",
+                      "candidates": cands[0], "ray_steps": steps[0]},
+           "design": {"beta": b, "gamma": g, "rmse_lsa": e, "levels": len(per),
+                      "wall_s": round(wall, 3)},
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                        "traffic": None, "algo_flops_per_ray_step": N2P_FLOPS_PER_STEP,
+                        "kernel": "n2p_sweep_kernel",
+                        "note": "1089 candidates x 10 rays = 10,890 lanes per launch: 170 "
+                                "waves for 1,024 SIMDs, so a level is latency-bound"}}
+    if not args.no_cpu_baseline:
+        import oracle  # CPU-baseline leg only
+        from concurrent.futures import ThreadPoolExecutor
+
+        oracle.build(force=False)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        bs = np.linspace(0.2, 2.5, 33)
+        gs = np.linspace(0.5, 8.0, 33)
+        cand = [(bb, gg) for bb in bs for gg in gs][:cpu_candidates]
+        rays = workloads.n2p_rays(L)
+
+        def one(c):
+            r = oracle.trace(workloads.n2p_lens(c[0], c[1], L), rays,
+                             {"dL0": 1e-4, "max_steps": 200000}, n_threads=1)
+            return int(r["steps"].sum())
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            n_steps = sum(ex.map(one, cand))
+        sec = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n_steps / sec, "unit": "ray-steps/s", "cores": threads,
+                               "kind": "oracle", "seconds": round(sec, 3),
+                               "sample": f"first {len(cand)} candidates of the first refinement "
+                                         f"level ({n_steps} ray-steps), FP64 C oracle, one "
+                                         f"candidate per thread, {threads} threads"}
+    ctx.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="freeform",
-                    choices=["freeform", "grid", "luneburg", "served"])
+                    choices=["freeform", "grid", "luneburg", "served", "n2p"])
     ap.add_argument("--jobs", type=int, default=120, help="served: jobs in the arrival stream")
     ap.add_argument("--load", type=float, default=0.8,
                     help="served: offered load as a fraction of the measured capacity")
@@ -337,6 +430,9 @@ def main(argv=None):
         return 1
     if args.workload == "served":
         print(json.dumps(served_bench(vrt, torch, args)), flush=True)
+        return 0
+    if args.workload == "n2p":
+        print(json.dumps(n2p_bench(vrt, torch, args)), flush=True)
         return 0
     spec, rays, prm, precision, desc, aperture = build_workload(args.workload, args.rays)
     n_rays = rays[0].shape[0]

@@ -63,7 +63,15 @@ enum vrt_medium_kind {
     VRT_MEDIUM_FIBER = 3,       /* params [n_c, Delta, R, cx, cy]      Sec. IV, Eq. (21), axis z   */
     VRT_MEDIUM_GAUSSIAN = 4,    /* params [n0, K, (A, sigma, cx, cy, cz) x K], K <= VRT_MAX_BUMPS
                                    n = n0 + sum A exp(-|P-c|^2 / (2 sigma^2))                     */
-    VRT_MEDIUM_GRID = 5         /* discretized medium, see vrt_medium_create_grid                  */
+    VRT_MEDIUM_GRID = 5,        /* discretized medium, see vrt_medium_create_grid                  */
+    VRT_MEDIUM_SPHERICAL = 6,   /* params [a0, a1, a2, a3, cx, cy, cz]  Sec. V, Eq. (26): spherical
+                                 * freeform n = a0 + a1 G1 + a2 G2 + a3 G3 about c,
+                                 * G1 = 0.3 (r^2 - 1), G2 = r cos(5 theta), G3 = r^2 sin^2(theta)
+                                 * cos(2 phi); the gradient is undefined at r = 0 (case (ii)) */
+    VRT_MEDIUM_N2P = 7          /* params [R, F, beta, gamma]  Sec. VI, Eq. (27): cylindrical N2P
+                                 * lens n = [1 + ((R^2 - (rho/2)^2) / F^2)^beta]^gamma, rho the
+                                 * distance from the z axis; the lens volume is the boundary
+                                 * (cylinder 0 <= rho <= R), n_ambient the surroundings (1) */
 };
 #define VRT_MAX_BUMPS 64
 
@@ -200,6 +208,65 @@ int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, s
  * synchronises that stream.  Errors: EINVAL, EHIP. */
 int vrt_reduce_counters(vrt_context_t ctx, const vrt_rays *rays, size_t n_rays,
                         vrt_counters *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Design sweep of the cylindrical N2P-GRIN lens (Sec. VI, Eqs. (27)-(29)).
+ *
+ * `lens` is a VRT_MEDIUM_N2P medium (its R and F, its cylinder boundary on the
+ * z axis from z0 = -L to z1 = 0, its surroundings) whose beta and gamma are
+ * replaced, candidate by candidate, by beta_gamma[2c], beta_gamma[2c + 1]
+ * (host array, n_cand pairs).  For each candidate, n_rays rays are launched
+ * parallel to the axis from (0, y[i], z_launch) (host array of heights;
+ * z_launch < z0) and traced with the plain FP64 march (p->precision VRT_FP64,
+ * no exit plane).  z_int,i is the axial coordinate where the exit line of ray
+ * i crosses the optical axis (the line is followed forwards only), and
+ * rmse[c] = sqrt(mean_i (F - z_int,i)^2) (host array, n_cand values), or +inf
+ * when a ray does not exit or does not head towards the axis.  z_int (host,
+ * n_cand * n_rays, candidate-major) and steps (host, n_cand: the ray-steps
+ * of each candidate's rays) are optional (NULL).  One launch on `stream`,
+ * synchronised before returning; the few device buffers are allocated per
+ * call.  Errors: EINVAL (arguments), EHIP.
+ * --------------------------------------------------------------------------- */
+int vrt_n2p_sweep(vrt_medium_t lens, const double *beta_gamma, size_t n_cand, const double *y,
+                  size_t n_rays, double z_launch, const vrt_trace_params *p, double *rmse,
+                  double *z_int, uint64_t *steps, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Gradient of an exit-plane loss with respect to a grid medium's node values
+ * (the direct-design use of the march, Sec. VI, made differentiable).
+ *
+ * For rays j with launch state (P0_j, d0_j) and target point t_j on the exit
+ * plane z = p->exit_plane_z, the plain FP64 march (Sec. II) gives the point
+ * x_j where ray j meets the plane; the loss is L = scale * sum_j |x_j - t_j|^2
+ * (x, y components), rays that do not reach the plane contributing 0.  The
+ * gradient is that of the discrete march with its branch pattern held fixed
+ * (Snell / TIR / straight decisions, step counts, surface events): the march
+ * is piecewise smooth in the node values and this is its derivative wherever
+ * no decision flips.  Computed by a hand-written reverse sweep: each ray's
+ * state is checkpointed every checkpoint_every steps, each interval is
+ * replayed from its checkpoint (bit for bit the forward march) and walked
+ * backwards through the vector-Jacobian product of each operation.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+    const double *px, *py, *pz, *dx, *dy, *dz; /* launch states (device, n_rays each) */
+    const double *tx, *ty;                     /* target point on the exit plane (device) */
+    double *loss_ray;                          /* out (device, n_rays): |x_j - t_j|^2, 0 when
+                                                  the ray misses the plane; may be NULL */
+    int32_t *end;                              /* out (device, n_rays): 1 reached the plane,
+                                                  2 did not; may be NULL */
+} vrt_adjoint_rays;
+
+/* grid: a VRT_MEDIUM_GRID medium in a box (its node values are the
+ * parameters).  p: VRT_FP64, an exit plane, eps_tan = 0, max_steps <= 1e6.
+ * *loss (host) receives L.  grad: device array of nz*ny*nx doubles (x
+ * fastest), overwritten with dL/dv; NULL computes the loss only.  Runs on
+ * `stream` and synchronises it; device scratch (checkpoints and tapes of up
+ * to 65,536 rays at a time: about (2 max_steps / (2 checkpoint_every) + 2 +
+ * 2 checkpoint_every) x 96 B per ray) is allocated per call.  Errors: EINVAL
+ * (arguments), ENOMEM, EHIP. */
+int vrt_grid_loss_grad(vrt_medium_t grid, const vrt_trace_params *p, const vrt_adjoint_rays *rays,
+                       size_t n_rays, double scale, int checkpoint_every, double *loss,
+                       double *grad, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of trace jobs.

@@ -20,7 +20,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvrt.so")
 
 VRT_OK, VRT_EINVAL, VRT_ENOMEM, VRT_EHIP, VRT_EUNSUPPORTED, VRT_ETIMEOUT = 0, -1, -2, -3, -4, -5
-MEDIUM_KINDS = {"homogeneous": 0, "linear": 1, "luneburg": 2, "fiber": 3, "gaussian": 4, "grid": 5}
+MEDIUM_KINDS = {"homogeneous": 0, "linear": 1, "luneburg": 2, "fiber": 3, "gaussian": 4, "grid": 5,
+                "spherical": 6, "n2p": 7}
 BOUNDARY_KINDS = {"box": 0, "sphere": 1, "cylinder": 2}
 VRT_FP64, VRT_FP32_COMP = 0, 1
 PRECISIONS = {"fp64": VRT_FP64, "fp32c": VRT_FP32_COMP}
@@ -33,7 +34,7 @@ EXPORTED = ["vrt_abi_version", "vrt_context_create", "vrt_context_destroy",
             "vrt_medium_create_analytic", "vrt_medium_create_grid", "vrt_medium_destroy",
             "vrt_medium_device_bytes", "vrt_trace", "vrt_reduce_counters", "vrt_last_error",
             "vrt_server_create", "vrt_server_submit", "vrt_server_query", "vrt_server_wait",
-            "vrt_server_stats_get", "vrt_server_destroy"]
+            "vrt_server_stats_get", "vrt_server_destroy", "vrt_n2p_sweep", "vrt_grid_loss_grad"]
 JOB_STATES = {0: "QUEUED", 1: "RUNNING", 2: "COPYING", 3: "DONE"}
 
 
@@ -62,6 +63,11 @@ class vrt_rays(C.Structure):
 COUNTER_FIELDS = ["rays", "steps", "exited", "missed", "truncated", "no_plane", "invalid",
                   "reflected_at_entry", "tir_interior", "tir_boundary", "flagged_near_critical",
                   "tangent", "straight", "flagged_near_tie", "flagged_near_grazing"]
+
+
+class vrt_adjoint_rays(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("px", "py", "pz", "dx", "dy", "dz", "tx", "ty",
+                                          "loss_ray", "end")]
 
 
 class vrt_counters(C.Structure):
@@ -120,6 +126,12 @@ def load_library(path=LIB_PATH):
     lib.vrt_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(vrt_job_info)]
     lib.vrt_server_stats_get.argtypes = [vp, C.POINTER(vrt_server_stats)]
     lib.vrt_server_destroy.argtypes = [vp]
+    lib.vrt_grid_loss_grad.argtypes = [vp, C.POINTER(vrt_trace_params), C.POINTER(vrt_adjoint_rays),
+                                       C.c_size_t, C.c_double, i32, C.POINTER(C.c_double), vp, vp]
+    dp = C.POINTER(C.c_double)
+    lib.vrt_n2p_sweep.argtypes = [vp, dp, C.c_size_t, dp, C.c_size_t, C.c_double,
+                                  C.POINTER(vrt_trace_params), dp, dp,
+                                  C.POINTER(C.c_uint64), vp]
     lib.vrt_last_error.restype = C.c_char_p
     lib.vrt_last_error.argtypes = []
     for name in EXPORTED:
@@ -188,6 +200,37 @@ def vrt_medium_device_bytes(m):
 def vrt_trace(medium, params, rays, n_rays, stream):
     return _check(load_library().vrt_trace(medium, C.byref(params), C.byref(rays), int(n_rays),
                                            C.c_void_p(stream)))
+
+
+def vrt_n2p_sweep(lens, beta_gamma, y, z_launch, params, stream=0, want_z=False,
+                  want_steps=False):
+    """RMSE_LSA per (beta, gamma) candidate, then (if asked) the axis
+    crossings (n_cand, n_rays) and the ray-steps per candidate."""
+    import numpy as np
+
+    bg = np.ascontiguousarray(beta_gamma, dtype=np.float64).reshape(-1, 2)
+    yy = np.ascontiguousarray(y, dtype=np.float64).ravel()
+    rmse = np.zeros(bg.shape[0])
+    z = np.zeros((bg.shape[0], yy.size)) if want_z else None
+    st = np.zeros(bg.shape[0], dtype=np.uint64) if want_steps else None
+    dp = C.POINTER(C.c_double)
+    _check(load_library().vrt_n2p_sweep(
+        lens, bg.ctypes.data_as(dp), bg.shape[0], yy.ctypes.data_as(dp), yy.size,
+        float(z_launch), C.byref(params), rmse.ctypes.data_as(dp),
+        z.ctypes.data_as(dp) if want_z else None,
+        st.ctypes.data_as(C.POINTER(C.c_uint64)) if want_steps else None, C.c_void_p(stream)))
+    out = (rmse,) + ((z,) if want_z else ()) + ((st,) if want_steps else ())
+    return out if len(out) > 1 else rmse
+
+
+def vrt_grid_loss_grad(grid, params, rays, n_rays, scale, checkpoint_every, grad_ptr, stream):
+    """Exit-plane loss (returned) and, when grad_ptr is not 0, dL/d(node values)
+    written to the device array at grad_ptr."""
+    loss = C.c_double()
+    _check(load_library().vrt_grid_loss_grad(grid, C.byref(params), C.byref(rays), int(n_rays),
+                                             float(scale), int(checkpoint_every), C.byref(loss),
+                                             C.c_void_p(grad_ptr or None), C.c_void_p(stream)))
+    return loss.value
 
 
 def vrt_server_create(ctx, hbm_budget, max_lanes=0):
@@ -289,6 +332,94 @@ class Medium:
         if self.handle is not None:
             vrt_medium_destroy(self.handle)
             self.handle = None
+
+
+def _grid_from_device(ctx, values, lo, hi, n_amb):
+    """A grid medium built on the device from a (nz, ny, nx) float32 CUDA tensor."""
+    nz, ny, nx = values.shape
+    return vrt_medium_create_grid(ctx.handle, values.data_ptr(), nx, ny, nz, lo, hi, n_amb, 1)
+
+
+class ExitPlaneLoss:
+    """L(v) = scale * sum_j |x_j(v) - t_j|^2: rays (P0, d0) marched in FP64
+    through the grid medium whose node values are v (a (nz, ny, nx) float32
+    CUDA tensor, nodes spanning lo..hi, surroundings n_amb) to the exit plane
+    z = params["exit_plane_z"], where ray j lands at x_j; t_j its target.
+    Calling it returns L as a torch scalar that backpropagates to v through
+    the library's adjoint (vrt_grid_loss_grad)."""
+
+    def __init__(self, ctx, P0, d0, targets, params, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                 n_amb=1.0, scale=None, checkpoint_every=64):
+        torch = _torch()
+        self.ctx = ctx
+        P0 = torch.as_tensor(P0, dtype=torch.float64)
+        d0 = torch.as_tensor(d0, dtype=torch.float64)
+        tg = torch.as_tensor(targets, dtype=torch.float64)
+        self.n = P0.shape[0]
+        self.buf = torch.empty((8, self.n), dtype=torch.float64, device="cuda")
+        self.buf[0:3].copy_(P0.T)
+        self.buf[3:6].copy_(d0.T)
+        self.buf[6:8].copy_(tg.T)
+        self.loss_ray = torch.zeros(self.n, dtype=torch.float64, device="cuda")
+        self.end = torch.zeros(self.n, dtype=torch.int32, device="cuda")
+        self.rays = vrt_adjoint_rays()
+        for i, k in enumerate(("px", "py", "pz", "dx", "dy", "dz", "tx", "ty")):
+            setattr(self.rays, k, self.buf[i].data_ptr())
+        self.rays.loss_ray = self.loss_ray.data_ptr()
+        self.rays.end = self.end.data_ptr()
+        self.params = make_params(params, "fp64")
+        self.lo, self.hi, self.n_amb = lo, hi, n_amb
+        self.scale = 1.0 / max(self.n, 1) if scale is None else float(scale)
+        self.checkpoint_every = int(checkpoint_every)
+
+    def evaluate(self, values, grad=None):
+        """Loss at values (float); the gradient into `grad` (float64 tensor of
+        the same shape) when given."""
+        torch = _torch()
+        v = values.detach().to(torch.float32).contiguous()
+        med = _grid_from_device(self.ctx, v, self.lo, self.hi, self.n_amb)
+        try:
+            return vrt_grid_loss_grad(med, self.params, self.rays, self.n, self.scale,
+                                      self.checkpoint_every,
+                                      grad.data_ptr() if grad is not None else 0,
+                                      torch.cuda.current_stream().cuda_stream)
+        finally:
+            vrt_medium_destroy(med)
+
+    def __call__(self, values):
+        return _ExitPlaneLossFn.apply(values, self)
+
+
+def _make_loss_fn():
+    torch = _torch()
+
+    class Fn(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, values, spec):
+            fctx.save_for_backward(values)
+            fctx.spec = spec
+            return torch.tensor(spec.evaluate(values), dtype=torch.float64, device=values.device)
+
+        @staticmethod
+        def backward(fctx, gout):
+            (values,) = fctx.saved_tensors
+            g = torch.empty(values.shape, dtype=torch.float64, device=values.device)
+            fctx.spec.evaluate(values, g)
+            return (gout * g).to(values.dtype), None
+
+    return Fn
+
+
+class _LazyFn:
+    fn = None
+
+    def apply(self, *a):
+        if _LazyFn.fn is None:
+            _LazyFn.fn = _make_loss_fn()
+        return _LazyFn.fn.apply(*a)
+
+
+_ExitPlaneLossFn = _LazyFn()
 
 
 def make_params(p, precision):

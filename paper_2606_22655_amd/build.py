@@ -15,7 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvrt.so")
-SOURCES = ["vrt_api.hip", "march_fp64.hip", "march_fp32c.hip", "serve.hip"]
+SOURCES = ["vrt_api.hip", "march_fp64.hip", "march_fp32c.hip", "serve.hip", "design.hip",
+           "adjoint.hip"]
 ARCH = os.environ.get("VRT_OFFLOAD_ARCH", "gfx950")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 

@@ -100,6 +100,8 @@ hipError_t launch_march_fp32c(const LaunchArgs &a) {
     case VRT_MEDIUM_FIBER: return launch32<VRT_MEDIUM_FIBER>(a);
     case VRT_MEDIUM_GAUSSIAN: return launch32<VRT_MEDIUM_GAUSSIAN>(a);
     case VRT_MEDIUM_GRID: return launch32<VRT_MEDIUM_GRID>(a);
+    case VRT_MEDIUM_SPHERICAL: return launch32<VRT_MEDIUM_SPHERICAL>(a);
+    case VRT_MEDIUM_N2P: return launch32<VRT_MEDIUM_N2P>(a);
     }
     return hipErrorInvalidValue;
 }

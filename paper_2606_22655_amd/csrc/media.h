@@ -19,6 +19,7 @@
 // Parameter storage (MediumDev.q, raw as given to vrt_medium_create_analytic):
 //   HOMOGENEOUS [n]  LINEAR [n0, gx, gy, gz]  LUNEBURG [R, cx, cy, cz]
 //   FIBER [n_c, Delta, R, cx, cy]  GAUSSIAN [n0] + bumps_d (A, sigma, cx, cy, cz) x K
+//   SPHERICAL [a0, a1, a2, a3, cx, cy, cz]  N2P [R, F, beta, gamma]
 // MedF.q holds single-precision derived constants (see vrt_api.hip).
 // Discretized media keep the node values and node records
 // (n, h_x, h_y, h_z) where h_a is the central difference of the node values
@@ -118,6 +119,38 @@ __device__ inline void med64(const MediumDev &m, d3 P, double &n, d3 &g) {
             g.y += -e * o.y / (s * s);
             g.z += -e * o.z / (s * s);
         }
+    } else if constexpr (MK == VRT_MEDIUM_SPHERICAL) {
+        // Sec. V, Eq. (26) in Cartesian form about the centre: with c = cos(theta) = z/r,
+        // G1 = 0.3 (r^2 - 1), G2 = r cos(5 theta) = z (16 c^4 - 20 c^2 + 5) (Chebyshev T5),
+        // G3 = r^2 sin^2(theta) cos(2 phi) = x^2 - y^2.  G2 is homogeneous of degree 1:
+        // its gradient is bounded but has no limit at r = 0 (returned as NaN: case (ii)).
+        const double a0 = p[0], a1 = p[1], a2 = p[2], a3 = p[3];
+        const double x = P.x - p[4], y = P.y - p[5], z = P.z - p[6];
+        const double r2 = x * x + y * y + z * z;
+        if (r2 == 0.0) {
+            n = a0 - 0.3 * a1;
+            g = mk(NAN, NAN, NAN);
+        } else {
+            const double c2 = z * z / r2;
+            n = a0 + a1 * (0.3 * (r2 - 1.0)) + a2 * (z * ((16.0 * c2 - 20.0) * c2 + 5.0)) +
+                a3 * (x * x - y * y);
+            const double h = z * c2 / r2 * (40.0 - 64.0 * c2);  // d G2/dx = h x, d G2/dy = h y
+            const double gz2 = ((-64.0 * c2 + 120.0) * c2 - 60.0) * c2 + 5.0;
+            g = mk(a1 * (0.6 * x) + a2 * (h * x) + a3 * (2.0 * x),
+                   a1 * (0.6 * y) + a2 * (h * y) - a3 * (2.0 * y), a1 * (0.6 * z) + a2 * gz2);
+        }
+    } else if constexpr (MK == VRT_MEDIUM_N2P) {
+        // Sec. VI, Eq. (27): n = u^gamma, u = 1 + w^beta, w = (R^2 - rho^2/4) / F^2 about the
+        // z axis; grad n = 2 dn/d(rho^2) (x, y, 0) with
+        // dn/d(rho^2) = gamma u^(gamma-1) beta w^(beta-1) (-1 / (4 F^2)).
+        const double R = p[0], F = p[1], be = p[2], ga = p[3];
+        const double rho2 = P.x * P.x + P.y * P.y;
+        const double w = (R * R - rho2 / 4.0) / (F * F);
+        const double wb = pow(w, be);
+        const double u = 1.0 + wb;
+        n = pow(u, ga);
+        const double k = 2.0 * (ga * (n / u) * be * (wb / w) * (-1.0 / (4.0 * F * F)));
+        g = mk(k * P.x, k * P.y, 0.0);
     } else {  // GRID: trilinear n, trilinear node central differences
         int c[3];
         double f[3];
@@ -219,6 +252,20 @@ __device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf, BumpPt
         } else {
             dn = n - n_last;
         }
+    } else if constexpr (MK == VRT_MEDIUM_SPHERICAL || MK == VRT_MEDIUM_N2P) {
+        // evaluated in double: n, grad n at P_i and the index difference as the
+        // difference of the double indices at P_i and P_i - s (error ~1e-16,
+        // far below the single-precision step)
+        const d3 P64 = mk((double)P.x, (double)P.y, (double)P.z);
+        const d3 Pp64 = mk(P64.x - (double)s.x, P64.y - (double)s.y, P64.z - (double)s.z);
+        double n64, np64;
+        d3 g64, gp64;
+        med64<MK>(m, P64, n64, g64);
+        med64<MK>(m, Pp64, np64, gp64);
+        n = (float)n64;
+        g = mkf((float)g64.x, (float)g64.y, (float)g64.z);
+        dn = (float)(n64 - np64);
+        (void)n_last;
     } else if constexpr (MK == VRT_MEDIUM_GAUSSIAN) {
         // E_k(P_{i-1}) = E_k(P_i) exp(dq_k), dq_k = ((P_i - c_k).s - |s|^2/2) / sigma^2,
         // so n_i - n_{i-1} = -sum A_k E_k(P_i) expm1(dq_k), with A_k expm1 as a

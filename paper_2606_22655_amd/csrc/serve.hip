@@ -480,6 +480,8 @@ __global__ __launch_bounds__(256, kServeOcc) void serve_kernel(const JobDesc *hd
             case VRT_MEDIUM_LUNEBURG: march_group<VRT_MEDIUM_LUNEBURG>(c, Dl, B, group); break;
             case VRT_MEDIUM_FIBER: march_group<VRT_MEDIUM_FIBER>(c, Dl, B, group); break;
             case VRT_MEDIUM_GAUSSIAN: march_group<VRT_MEDIUM_GAUSSIAN>(c, Dl, B, group); break;
+            case VRT_MEDIUM_SPHERICAL: march_group<VRT_MEDIUM_SPHERICAL>(c, Dl, B, group); break;
+            case VRT_MEDIUM_N2P: march_group<VRT_MEDIUM_N2P>(c, Dl, B, group); break;
             default: march_group<VRT_MEDIUM_GRID>(c, Dl, B, group); break;
             }
             idle = 0;

@@ -207,10 +207,10 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
         return fail(VRT_EINVAL, "vrt_medium_create_analytic: params missing or non-finite");
     if (!(n_ambient > 0.0) || !isfinite(n_ambient))
         return fail(VRT_EINVAL, "n_ambient must be finite and > 0");
-    static const int need[] = {1, 4, 4, 5, -1};
-    if (kind < VRT_MEDIUM_HOMOGENEOUS || kind > VRT_MEDIUM_GAUSSIAN)
-        return fail(kind == VRT_MEDIUM_GRID ? VRT_EINVAL : VRT_EINVAL,
-                    "analytic medium kind %d unknown (grids use vrt_medium_create_grid)", kind);
+    static const int need[] = {1, 4, 4, 5, -1, -1, 7, 4};
+    if (kind < VRT_MEDIUM_HOMOGENEOUS || kind > VRT_MEDIUM_N2P || kind == VRT_MEDIUM_GRID)
+        return fail(VRT_EINVAL, "analytic medium kind %d unknown (grids use vrt_medium_create_grid)",
+                    kind);
     if (kind != VRT_MEDIUM_GAUSSIAN && n_params != need[kind])
         return fail(VRT_EINVAL, "medium kind %d needs %d params, got %d", kind, need[kind], n_params);
     BoundaryDev b;
@@ -266,6 +266,19 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
         f.q[7] = (float)(R * R);
         break;
     }
+    case VRT_MEDIUM_SPHERICAL:
+        // Sec. V, Eq. (26); evaluated in double on both paths (media.h)
+        for (int i = 0; i < 7; ++i) d.q[i] = p[i];
+        break;
+    case VRT_MEDIUM_N2P:
+        // Sec. VI, Eq. (27); w = (R^2 - rho^2/4)/F^2 > 0 for rho < 2R, which the lens
+        // (rho <= R) keeps
+        if (!(p[0] > 0.0) || !(p[1] > 0.0)) {
+            delete m;
+            return fail(VRT_EINVAL, "N2P lens needs R > 0 and F > 0");
+        }
+        for (int i = 0; i < 4; ++i) d.q[i] = p[i];
+        break;
     case VRT_MEDIUM_GAUSSIAN: {
         if (n_params < 2) {
             delete m;

@@ -1,0 +1,259 @@
+"""GPU: gradient of the exit-plane loss with respect to the node values of a
+grid medium (vrt_grid_loss_grad, the differentiable design configuration:
+64^3 grid 1.5 + 0.01 N(0,1), parallel rays along +z, exit plane z = 1.2,
+targets on a ring).
+
+The march is piecewise smooth in the node values: the gradient is that of the
+discrete march with its branch pattern fixed.  Finite differences are
+compared per ray, only on rays whose difference quotient is in its linear
+regime -- same status and TIR counts at v +- h and v +- h/2, and the two
+quotients agreeing -- since near-critical refraction makes the derivative
+grow as 1/sqrt(D) and a quotient across it measures nothing."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vrt():
+    import torch
+
+    import paper_2606_22655_amd as vrt
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    vrt.load_library()
+    return vrt
+
+
+@pytest.fixture(scope="module")
+def ctx(vrt):
+    c = vrt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def problem():
+    med, (P0, d0), prm, tgt = workloads.design_problem(n_side=128, max_steps=10000)
+    return med, P0, d0, prm, tgt
+
+
+def trace_fp64(vrt, ctx, values, P0, d0, prm):
+    """Per-ray exit-plane points and events from the plain FP64 trace."""
+    import torch
+
+    spec = workloads.grid_medium(values)
+    med = vrt.Medium(ctx, spec)
+    try:
+        b = vrt.RayBatch(P0, d0, "fp64")
+        vrt.trace(med, b, prm, "fp64")
+        torch.cuda.synchronize()
+        return b.results()
+    finally:
+        med.close()
+
+
+def ray_loss(res, tgt):
+    ok = res["status"] == 0  # EXITED (to the plane)
+    d = res["P"][:, :2] - tgt
+    return np.where(ok, (d * d).sum(axis=1), 0.0), ok
+
+
+def adjoint(vrt, ctx, values, P0, d0, prm, tgt, scale, K=64):
+    import torch
+
+    f = vrt.ExitPlaneLoss(ctx, P0, d0, tgt, prm, scale=scale, checkpoint_every=K)
+    v = torch.as_tensor(values, device="cuda")
+    g = torch.empty(v.shape, dtype=torch.float64, device="cuda")
+    L = f.evaluate(v, g)
+    torch.cuda.synchronize()
+    return L, g.cpu().numpy(), f.loss_ray.cpu().numpy(), f.end.cpu().numpy()
+
+
+def test_forward_loss_equals_the_plain_trace(vrt, ctx, problem):
+    med, P0, d0, prm, tgt = problem
+    L, _, lr, end = adjoint(vrt, ctx, med["grid"], P0, d0, prm, tgt, 1.0 / len(P0))
+    res = trace_fp64(vrt, ctx, med["grid"], P0, d0, prm)
+    l0, ok = ray_loss(res, tgt)
+    assert np.array_equal(end == 1, ok)
+    assert np.abs(lr - l0).max() < 1e-15
+    assert L == pytest.approx(l0.sum() / len(P0), rel=1e-13)
+
+
+def fd_rays(vrt, ctx, values, flat, h, P0, d0, prm, tgt):
+    """Per-ray central difference quotient of the loss at node `flat` with step
+    h (float32 values, the step actually taken), and the branch signature."""
+    vp = values.copy().ravel()
+    vm = values.copy().ravel()
+    vp[flat] += np.float32(h)
+    vm[flat] -= np.float32(h)
+    hh = float(vp[flat]) - float(vm[flat])
+    rp = trace_fp64(vrt, ctx, vp.reshape(values.shape), P0, d0, prm)
+    rm = trace_fp64(vrt, ctx, vm.reshape(values.shape), P0, d0, prm)
+    lp, _ = ray_loss(rp, tgt)
+    lm, _ = ray_loss(rm, tgt)
+    sig = [(r["status"], r["ntir"], r["nbtir"]) for r in (rp, rm)]
+    return (lp - lm) / hh, sig
+
+
+def linear_rays(q1, q2, sigs, base):
+    same = np.ones(len(q1), dtype=bool)
+    for s in sigs:
+        for a, b in zip(s, base):
+            same &= a == b
+    tol = 1e-3 * np.maximum(np.abs(q2), 1e-9)
+    return same & (np.abs(q1 - q2) <= tol)
+
+
+def test_gradient_matches_finite_differences(vrt, ctx, problem):
+    """32 seeded nodes (seed 304), central differences with h = 1e-4 and
+    h / 2 on the plain FP64 trace; Richardson-extrapolated quotients of the
+    linear rays against the adjoint of the same rays."""
+    med, P0, d0, prm, tgt = problem
+    values = med["grid"]
+    n = len(P0)
+    base_res = trace_fp64(vrt, ctx, values, P0, d0, prm)
+    base = (base_res["status"], base_res["ntir"], base_res["nbtir"])
+    nodes = np.random.default_rng(304).choice(values.size, 32, replace=False)
+    checked = worst = 0.0
+    set_aside = []
+    for flat in nodes:
+        q1, s1 = fd_rays(vrt, ctx, values, flat, 1e-4, P0, d0, prm, tgt)
+        q2, s2 = fd_rays(vrt, ctx, values, flat, 5e-5, P0, d0, prm, tgt)
+        lin = linear_rays(q1, q2, s1 + s2, base)
+        set_aside.append(int((~lin & ((q1 != 0) | (q2 != 0))).sum()))
+        qr = ((4 * q2 - q1) / 3)[lin]
+        fd = qr.sum() / n
+        _, g, _, _ = adjoint(vrt, ctx, values, P0[lin], d0[lin], prm, tgt[lin], 1.0 / n)
+        err = abs(g.ravel()[flat] - fd)
+        scale = max(np.abs(qr).sum() / n, 1e-9)  # the size of the rays' contributions
+        print(f"[adjoint] node {flat}: adjoint {g.ravel()[flat]:.6e} fd {fd:.6e} "
+              f"(sum |per ray| {scale:.3e}, {set_aside[-1]} rays set aside)", flush=True)
+        worst = max(worst, err / scale)
+        checked += 1
+    print(f"[adjoint] worst error / contribution size: {worst:.3e}", flush=True)
+    assert worst < 1e-3
+    assert np.mean(set_aside) < 0.05 * n
+
+
+def test_gradient_matches_the_oracle(vrt, ctx, orc, problem):
+    """The FP64 oracle's own difference quotients (its march, h = 1e-5 and
+    5e-6) on 8,192 of the rays, linear rays only, against the adjoint."""
+    med, P0, d0, prm, tgt = problem
+    values = med["grid"]
+    sel = np.arange(0, len(P0), 2)
+    P0s, d0s, tgs = P0[sel], d0[sel], tgt[sel]
+    n = len(sel)
+    _, g_all, _, _ = adjoint(vrt, ctx, values, P0s, d0s, prm, tgs, 1.0 / n)
+    # 6 seeded nodes among those these rays depend on
+    nodes = np.random.default_rng(305).choice(np.nonzero(g_all.ravel())[0], 6, replace=False)
+    compared = 0
+
+    def oracle_q(flat, h):
+        vp = values.copy().ravel()
+        vm = values.copy().ravel()
+        vp[flat] += np.float32(h)
+        vm[flat] -= np.float32(h)
+        hh = float(vp[flat]) - float(vm[flat])
+        rp = orc.trace(workloads.grid_medium(vp.reshape(values.shape)), (P0s, d0s), prm)
+        rm = orc.trace(workloads.grid_medium(vm.reshape(values.shape)), (P0s, d0s), prm)
+        lp, _ = ray_loss(rp, tgs)
+        lm, _ = ray_loss(rm, tgs)
+        return (lp - lm) / hh, [(r["status"], r["ntir"], r["nbtir"]) for r in (rp, rm)]
+
+    o = orc.trace(workloads.grid_medium(values), (P0s, d0s), prm)
+    base = (o["status"], o["ntir"], o["nbtir"])
+    for flat in nodes:
+        q1, s1 = oracle_q(flat, 1e-5)
+        q2, s2 = oracle_q(flat, 5e-6)
+        lin = linear_rays(q1, q2, s1 + s2, base)
+        qr = ((4 * q2 - q1) / 3)[lin]
+        fd = qr.sum() / n
+        _, g, _, _ = adjoint(vrt, ctx, values, P0s[lin], d0s[lin], prm, tgs[lin], 1.0 / n)
+        scale = max(np.abs(qr).sum() / n, 1e-9)
+        print(f"[adjoint] oracle node {flat}: adjoint {g.ravel()[flat]:.6e} oracle fd {fd:.6e} "
+              f"(sum |per ray| {scale:.3e}, {int((~lin).sum())} rays set aside)", flush=True)
+        assert abs(g.ravel()[flat] - fd) <= 1e-3 * scale
+        compared += fd != 0.0
+    assert compared >= 3
+
+
+def test_checkpoint_interval_does_not_change_the_gradient(vrt, ctx, problem):
+    med, P0, d0, prm, tgt = problem
+    sel = np.arange(0, len(P0), 4)
+    ref = None
+    for K in (1, 16, 64, 4096):
+        L, g, _, _ = adjoint(vrt, ctx, med["grid"], P0[sel], d0[sel], prm, tgt[sel],
+                             1.0 / len(sel), K=K)
+        if ref is None:
+            ref = (L, g)
+        else:
+            assert L == ref[0]
+            assert np.abs(g - ref[1]).max() <= 1e-10 * np.abs(ref[1]).max()
+
+
+def test_autograd_backward_and_a_descent_step(vrt, ctx):
+    """Through torch.autograd: the gradient equals the direct call, and a
+    small step against it lowers the loss.  The medium is graded along z with
+    a weak transverse ripple (32^3 nodes, n = 1.5 + 0.05 z + 0.002
+    sin(2 pi x) cos(2 pi y)) and the rays are tilted 10 deg, so every
+    refraction is far from critical and the loss is smooth."""
+    import math
+
+    import torch
+
+    N = 32
+    k = np.linspace(0.0, 1.0, N)
+    Z, Y, X = np.meshgrid(k, k, k, indexing="ij")
+    values = (1.5 + 0.05 * Z + 0.002 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)).astype(
+        np.float32)
+    n_side = 64
+    c = (np.arange(n_side) + 0.5) / n_side
+    XX, YY = np.meshgrid(c, c, indexing="xy")
+    P0 = np.stack([XX.ravel() * 0.8, YY.ravel(), np.zeros(XX.size)], axis=1)
+    a = math.radians(10.0)
+    d0 = np.tile([math.sin(a), 0.0, math.cos(a)], (len(P0), 1))
+    tgt = np.full((len(P0), 2), 0.5)
+    prm = workloads.trace_params(5e-4, 10000, exit_plane_z=1.2)
+    f = vrt.ExitPlaneLoss(ctx, P0, d0, tgt, prm)
+    v = torch.tensor(values, device="cuda", requires_grad=True)
+    L = f(v)
+    L.backward()
+    g = torch.empty(v.shape, dtype=torch.float64, device="cuda")
+    L2 = f.evaluate(v, g)
+    assert L.item() == L2
+    assert torch.equal(v.grad, g.float())
+    assert int(f.end.eq(1).sum()) == len(P0)
+    gn = float((g * g).sum())
+    eta = 1e-3 * L.item() / gn  # predicted decrease: 1e-3 L
+    with torch.no_grad():
+        v2 = (v.double() - eta * g).float()
+    L3 = f.evaluate(v2)
+    print(f"\n[adjoint] descent: L {L.item():.8e} -> {L3:.8e} (predicted "
+          f"{L.item() - eta * gn:.8e})", flush=True)
+    assert L3 < L.item()
+    assert (L.item() - L3) == pytest.approx(eta * gn, rel=0.1)
+
+
+def test_adjoint_refusals(vrt, ctx, problem):
+    import torch
+
+    med, P0, d0, prm, tgt = problem
+    f = vrt.ExitPlaneLoss(ctx, P0[:64], d0[:64], tgt[:64], prm)
+    v = torch.tensor(med["grid"], device="cuda")
+    for bad in ({"eps_tan": 1e-3}, {"exit_plane_z": None}):
+        g = vrt.ExitPlaneLoss(ctx, P0[:64], d0[:64], tgt[:64], dict(prm, **bad))
+        with pytest.raises(vrt.VrtError):
+            g.evaluate(v)
+    other = vrt.Medium(ctx, workloads.spherical_medium())
+    try:
+        with pytest.raises(vrt.VrtError):  # not a grid medium
+            vrt.vrt_grid_loss_grad(other.handle, f.params, f.rays, 64, 1.0, 64, 0, 0)
+        with pytest.raises(vrt.VrtError):  # checkpoint interval out of range
+            f.checkpoint_every = 0
+            f.evaluate(v)
+    finally:
+        other.close()

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads
-from parity import assert_parity, compare
+from parity import assert_parity, compare, exempt, ill_conditioned
 
 pytestmark = pytest.mark.gpu
 
@@ -36,8 +36,8 @@ def ctx(vrt):
 
 @pytest.fixture(scope="module")
 def media(vrt, ctx):
-    """Five media: Gaussian-bump cube, 48^3 quantized grid, Luneburg sphere,
-    fiber cylinder, linear slab."""
+    """Seven media: Gaussian-bump cube, 48^3 quantized grid, Luneburg sphere,
+    fiber cylinder, linear slab, spherical freeform sphere, N2P lens."""
     specs = [workloads.gaussian_medium(500), workloads.grid_medium(workloads.noise_grid(48, 504))]
     lun, _, _ = workloads.luneburg_beam(n_side=4)
     specs.append(lun)
@@ -47,6 +47,8 @@ def media(vrt, ctx):
     specs.append({"kind": "linear", "params": np.array([1.5, 0.05, -0.02, 0.1]),
                   "boundary": {"kind": "box", "params": np.array([0, 0, 0, 1, 1, 1.0])},
                   "n_amb": 1.0})
+    specs.append(workloads.spherical_medium())
+    specs.append(workloads.n2p_lens(0.6791, 5.0069, 0.2))
     meds = [vrt.Medium(ctx, s) for s in specs]
     yield specs, meds
     for m in meds:
@@ -58,7 +60,15 @@ def job_rays(spec, n, seed):
     kind = spec["boundary"]["kind"]
     if kind == "box":
         return workloads.face_cone_rays(n, seed, 25.0)
+    if spec["kind"] == "spherical":  # aimed into the ball from outside
+        return workloads.sphere_aimed_rays(n, seed)
     rng = np.random.default_rng(seed)
+    if spec["kind"] == "n2p":  # parallel rays onto the lens face
+        r = 0.95 * np.sqrt(rng.uniform(0.0, 1.0, n))
+        a = rng.uniform(0.0, 2 * np.pi, n)
+        z0 = spec["boundary"]["params"][3] - 0.1
+        return np.column_stack([r * np.cos(a), r * np.sin(a), np.full(n, z0)]), \
+            np.tile([0.0, 0.0, 1.0], (n, 1))
     if kind == "sphere":
         h = rng.uniform(-0.9, 0.9, (n, 2))
         return np.column_stack([h, np.full(n, -1.5)]), np.tile([0.0, 0.0, 1.0], (n, 1))
@@ -127,6 +137,12 @@ def test_served_results_meet_the_parity_bar(vrt, ctx, media):
         o = oracle.trace(specs[mi], rays, prm)
         if specs[mi]["kind"] == "grid":  # chaotic medium: identical only for short marches
             continue
+        if specs[mi]["kind"] == "spherical":
+            # repeated TIR in the sphere: leave out the rays whose oracle result
+            # moves by 1e-5 under a float32-sized (1e-7) launch shift
+            bad = ill_conditioned(oracle.trace, specs[mi], rays, prm, delta=1e-7, tol=1e-5)
+            assert bad.sum() <= 0.10 * len(bad)
+            o, r = exempt(o, bad), exempt(r, bad)
         ap = 2.0 if specs[mi]["boundary"]["kind"] == "sphere" else (
             10.0 if specs[mi]["kind"] == "fiber" else 1.0)
         assert_parity(compare(o, r, aperture=ap, spec=specs[mi]))
