@@ -2,7 +2,7 @@
 """Benchmark of the constant-OPL vectorial ray march on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload freeform|grid|luneburg|served|n2p]
+                    [--workload freeform|grid|luneburg|served|n2p|adjoint]
 
 A "step" of this benchmark is one pass of the whole hot path over one batch:
 one vrt_trace call that launches, enters, marches (medium evaluation, normal,
@@ -46,11 +46,11 @@ PEAK_HBM_GBS = 8000.0
 # plain 2 GiB device copy (FETCH_SIZE reads half the copied bytes: x2;
 # WRITE_SIZE reads them exactly: x1).  Valid only for the kernel sources they
 # were taken on (sha256 of the files below); reported as null otherwise.
-KERNEL_SOURCES = ("march_fp32c.hip", "media.h", "vrt_common.h", "dispatch.h")
+KERNEL_SOURCES = ("march_fp32c.hip", "lane32.h", "media.h", "vrt_common.h", "dispatch.h")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {  # workload -> (fetch KiB, write KiB, kernel sha256); profiles/march_fp32c_hbm_traffic.md
-    "freeform": (79749.3, 299428.1, "3907978953d2f3f7cccf527d3f8654bea236d0ad5dfc45efd2213bbb9284653b"),
-    "grid": (409733720.5, 1584197.1, "3907978953d2f3f7cccf527d3f8654bea236d0ad5dfc45efd2213bbb9284653b"),
+    "freeform": (80042.8, 322920.2, "b7f78697617e9b3867bb3aadf6cebf4de4f7a0d64ff083f8f5bb5bcf466b04e6"),
+    "grid": (409714898.7, 1584148.4, "b7f78697617e9b3867bb3aadf6cebf4de4f7a0d64ff083f8f5bb5bcf466b04e6"),
 }
 
 
@@ -401,13 +401,86 @@ def n2p_bench(vrt, torch, args, L=0.3, cpu_candidates=256):
     return out
 
 
+# ---------------------------------------------------------------------------
+# differentiable design: loss and gradient w.r.t. grid node values
+# ---------------------------------------------------------------------------
+ADJ_FLOPS_PER_STEP = 134  # the FP64 grid march step (as the grid workload's count)
+
+
+def adjoint_bench(vrt, torch, args):
+    """The differentiable design configuration: 64^3 grid 1.5 + 0.01 N(0,1),
+    512 x 512 parallel rays along +z, exit plane z = 1.2, targets on a ring,
+    dL0 = 5e-4, FP64.  Times the loss alone and the loss with its gradient
+    (forward with checkpoints every 64 steps, replay, reverse sweep)."""
+    med, (P0, d0), prm, tgt = workloads.design_problem(max_steps=10000)
+    ctx = vrt.Context(0)
+    f = vrt.ExitPlaneLoss(ctx, P0, d0, tgt, prm, checkpoint_every=64)
+    v = torch.tensor(med["grid"], device="cuda")
+    g = torch.empty(v.shape, dtype=torch.float64, device="cuda")
+    f.evaluate(v, g)  # warmup
+    steps_fwd = None
+    t_loss, t_grad = [], []
+    for k in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = f.evaluate(v)
+        torch.cuda.synchronize()
+        t_loss.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        L2 = f.evaluate(v, g)
+        torch.cuda.synchronize()
+        t_grad.append(time.perf_counter() - t0)
+        print(f"[adjoint] iteration {k}: loss {t_loss[-1] * 1e3:.1f} ms, loss+grad "
+              f"{t_grad[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    # ray-steps of the forward march (the same rays through the plain FP64 trace)
+    b = vrt.RayBatch(P0, d0, "fp64")
+    medium = vrt.Medium(ctx, med)
+    vrt.trace(medium, b, prm, "fp64")
+    steps_fwd = vrt.counters(ctx, b)["steps"]
+    medium.close()
+    tl, tg = float(np.median(t_loss)), float(np.median(t_grad))
+    value = steps_fwd / tg
+    out = {"metric": METRIC, "value": value, "unit": "ray-steps/s", "n_gpus": 1,
+           "steps": len(t_grad), "warmup": 1, "ms_per_step": round(tg * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "differentiable design: 64^3 grid 1.5 + 0.01 N(0,1), 512 x 512 "
+                                  "parallel rays along +z, exit plane z = 1.2, ring targets, "
+                                  "dL0 = 5e-4, FP64, gradient of the exit-plane loss w.r.t. the "
+                                  "262,144 node values, checkpoints every 64 steps",
+                      "rays": len(P0), "ray_steps": steps_fwd},
+           "loss": L2, "loss_only_ms": round(tl * 1e3, 3), "loss_and_grad_ms": round(tg * 1e3, 3),
+           "grad_over_loss_time": round(tg / tl, 3),
+           "roofline": {"bound": "alu", "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "achieved": round(ADJ_FLOPS_PER_STEP * steps_fwd / tl / 1e12, 3),
+                        "frac": round(ADJ_FLOPS_PER_STEP * steps_fwd / tl / 1e12 /
+                                      PEAK_FP64_TFLOPS, 4),
+                        "traffic": None, "kernel": "adj_forward_kernel (loss only)",
+                        "algo_flops_per_ray_step": ADJ_FLOPS_PER_STEP}}
+    if not args.no_cpu_baseline:
+        import oracle  # CPU-baseline leg only
+
+        oracle.build(force=False)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        n = 16384
+        r = oracle.trace(med, (P0[:n], d0[:n]), prm, n_threads=threads)
+        st = int(r["steps"].sum())
+        out["cpu_baseline"] = {"value": st / r["seconds"], "unit": "ray-steps/s", "cores": threads,
+                               "kind": "oracle", "seconds": round(r["seconds"], 3),
+                               "sample": f"first {n} rays, forward march only ({st} ray-steps): "
+                                         "the oracle has no adjoint; its gradient is two marches "
+                                         "per node value"}
+    ctx.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="freeform",
-                    choices=["freeform", "grid", "luneburg", "served", "n2p"])
+                    choices=["freeform", "grid", "luneburg", "served", "n2p", "adjoint"])
     ap.add_argument("--jobs", type=int, default=120, help="served: jobs in the arrival stream")
     ap.add_argument("--load", type=float, default=0.8,
                     help="served: offered load as a fraction of the measured capacity")
@@ -433,6 +506,9 @@ def main(argv=None):
         return 0
     if args.workload == "n2p":
         print(json.dumps(n2p_bench(vrt, torch, args)), flush=True)
+        return 0
+    if args.workload == "adjoint":
+        print(json.dumps(adjoint_bench(vrt, torch, args)), flush=True)
         return 0
     spec, rays, prm, precision, desc, aperture = build_workload(args.workload, args.rays)
     n_rays = rays[0].shape[0]

@@ -260,10 +260,10 @@ typedef struct {
  * parameters).  p: VRT_FP64, an exit plane, eps_tan = 0, max_steps <= 1e6.
  * *loss (host) receives L.  grad: device array of nz*ny*nx doubles (x
  * fastest), overwritten with dL/dv; NULL computes the loss only.  Runs on
- * `stream` and synchronises it; device scratch (checkpoints and tapes of up
- * to 65,536 rays at a time: about (2 max_steps / (2 checkpoint_every) + 2 +
- * 2 checkpoint_every) x 96 B per ray) is allocated per call.  Errors: EINVAL
- * (arguments), ENOMEM, EHIP. */
+ * `stream` and synchronises it; device scratch for the gradient
+ * (checkpoints and tapes, about (max_steps / checkpoint_every + 2 +
+ * 2 checkpoint_every) x 96 B per ray, for as many rays at a time as 8 GiB
+ * holds) is allocated per call.  Errors: EINVAL (arguments), ENOMEM, EHIP. */
 int vrt_grid_loss_grad(vrt_medium_t grid, const vrt_trace_params *p, const vrt_adjoint_rays *rays,
                        size_t n_rays, double scale, int checkpoint_every, double *loss,
                        double *grad, void *stream);

@@ -8,9 +8,10 @@
 // the interval's operations from the checkpoint -- bit for bit the forward
 // ones -- saving the state before each into a per-lane tape, then walks the
 // tape backwards applying each operation's vector-Jacobian product.  Grid
-// evaluations add their contributions to the node values and to the node
-// central differences (atomic adds into HBM); a last kernel folds the central
-// differences back onto the node values.
+// evaluations sum their contributions to the node values and node central
+// differences of the current cell in per-lane LDS accumulators, which are
+// added to the node arrays in HBM (atomically) when the ray changes cell; a
+// last kernel folds the central differences back onto the node values.
 #pragma clang fp contract(off)
 #include <string.h>
 
@@ -23,7 +24,7 @@ namespace vrt {
 namespace adj {
 
 constexpr int kF = 12;  // doubles per saved state
-constexpr uint32_t kChunk = 65536;  // rays per forward/backward launch pair
+constexpr size_t kScratchBudget = 8ull << 30;  // checkpoints + tapes of one launch pair
 
 struct AdjIn {
     const double *px, *py, *pz, *dx, *dy, *dz, *tx, *ty;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void adj_forward_kernel(MediumDev m, BoundaryD
 }
 
 // Reverse sweep of rays [r0, r0 + n) that reached the exit plane.
-__global__ __launch_bounds__(256) void adj_backward_kernel(MediumDev m, BoundaryDev b, TraceDev t,
+__global__ __launch_bounds__(256, 2) void adj_backward_kernel(MediumDev m, BoundaryDev b, TraceDev t,
                                                            AdjIn in, uint32_t r0, uint32_t n,
                                                            uint32_t kops, const double *ck,
                                                            const uint32_t *nops, const double *xy,
@@ -111,6 +112,9 @@ __global__ __launch_bounds__(256) void adj_backward_kernel(MediumDev m, Boundary
     const double xbar = 2.0 * scale * (xy[2 * lane] - in.tx[r]);
     const double ybar = 2.0 * scale * (xy[2 * lane + 1] - in.ty[r]);
     const uint32_t total = nops[lane];
+    // per-lane cell accumulators in LDS: slot q of thread x at [q][x]
+    __shared__ double acc_lds[32 * 256];
+    GradAcc acc = make_acc(acc_lds + threadIdx.x, blockDim.x, m, go);
     Adj a = zero_adj();
     for (int seg = (int)((total - 1) / kops); seg >= 0; --seg) {
         St s = get_state(ck, (uint32_t)seg, lane, n);
@@ -124,10 +128,11 @@ __global__ __launch_bounds__(256) void adj_backward_kernel(MediumDev m, Boundary
         }
         for (uint32_t o = o1; o-- > o0;) {
             const St si = get_state(tape, o - o0, lane, n);
-            vjp_op(m, b, t, si, a, xbar, ybar, go);
+            vjp_op(m, b, t, si, a, xbar, ybar, acc);
         }
     }
-    vjp_entry(m, b, t, mk(in.px[r], in.py[r], in.pz[r]), mk(in.dx[r], in.dy[r], in.dz[r]), a, go);
+    vjp_entry(m, b, t, mk(in.px[r], in.py[r], in.pz[r]), mk(in.dx[r], in.dy[r], in.dz[r]), a, acc);
+    acc.flush();
 }
 
 __global__ void fill_kernel(double *p, size_t n, double v) {
@@ -185,7 +190,12 @@ extern "C" int vrt_grid_loss_grad(vrt_medium_t grid, const vrt_trace_params *p,
     const size_t nodes = (size_t)m.nx * m.ny * m.nz;
     const uint32_t kops = 2u * (uint32_t)checkpoint_every;  // a step is a decision and a move
     const uint32_t n_ck = (uint32_t)((2 * p->max_steps + 1) / kops + 2);
-    const uint32_t lanes = (uint32_t)(n_rays < kChunk ? n_rays : kChunk);
+    // rays per forward/backward launch pair: all of them for the loss alone;
+    // with the gradient, as many as the scratch budget holds (at least 4,096)
+    const size_t per_lane = sizeof(double) * kF * ((size_t)n_ck + kops) + 32;
+    size_t cap = grad ? kScratchBudget / per_lane : n_rays;
+    cap = cap < 4096 ? 4096 : cap;
+    const uint32_t lanes = (uint32_t)(n_rays < cap ? n_rays : cap);
     double *loss_ray = rays->loss_ray, *own_loss = nullptr, *ck = nullptr, *tape = nullptr,
            *xy = nullptr, *gH = nullptr;
     uint32_t *nops = nullptr;

@@ -69,11 +69,59 @@ __device__ __forceinline__ void grad_add(double *p, double v) {
 #endif
 }
 
+// Per-lane accumulator of the node-gradient contributions of one cell: the
+// 8 corners x (v, H_x, H_y, H_z) of the cell the lane last evaluated in.
+// Consecutive steps of a ray mostly stay in one cell (a cell edge spans tens
+// of steps), so contributions are summed here and added to the node arrays
+// (atomically) only when the ray moves to another cell, and once at the end.
+struct GradAcc {
+    double *slot;     // 32 accumulators, `stride` apart
+    uint32_t stride;
+    int cell[3];      // cell held (cell[0] < 0: none)
+    GradOut go;
+    size_t nx, ny;
+
+    __device__ void flush() {
+        if (cell[0] < 0) return;
+        for (int corner = 0; corner < 8; ++corner) {
+            const int i = cell[0] + (corner & 1), j = cell[1] + ((corner >> 1) & 1),
+                      k = cell[2] + (corner >> 2);
+            const size_t node = ((size_t)k * ny + j) * nx + i;
+            double *q = slot + (size_t)(4 * corner) * stride;
+            if (q[0] != 0.0) grad_add(go.gv + node, q[0]);
+            if (q[stride] != 0.0) grad_add(go.gH + node, q[stride]);
+            if (q[2 * stride] != 0.0) grad_add(go.gH + go.nodes + node, q[2 * stride]);
+            if (q[3 * stride] != 0.0) grad_add(go.gH + 2 * go.nodes + node, q[3 * stride]);
+        }
+        cell[0] = -1;
+    }
+    __device__ void open(const int c[3]) {
+        if (cell[0] == c[0] && cell[1] == c[1] && cell[2] == c[2]) return;
+        flush();
+        for (int q = 0; q < 32; ++q) slot[(size_t)q * stride] = 0.0;
+        cell[0] = c[0];
+        cell[1] = c[1];
+        cell[2] = c[2];
+    }
+};
+
+__device__ inline GradAcc make_acc(double *slot, uint32_t stride, const MediumDev &m,
+                                   const GradOut &go) {
+    GradAcc a;
+    a.slot = slot;
+    a.stride = stride;
+    a.cell[0] = a.cell[1] = a.cell[2] = -1;
+    a.go = go;
+    a.nx = (size_t)m.nx;
+    a.ny = (size_t)m.ny;
+    return a;
+}
+
 // VJP of the grid evaluation at P (media.h, med64<GRID>): n = sum_k w_k v_k and
 // g_a = sum_k w_k H_a(k) over the 8 corners, w_k = prod_b (d_b ? f_b : 1 - f_b),
 // f_b = (x_b - lo_b) / h_b - c_b.  Adds to the node gradients and returns the
 // adjoint of P.
-__device__ inline d3 grid_vjp(const MediumDev &m, d3 P, double nbar, d3 gbar, const GradOut &go) {
+__device__ inline d3 grid_vjp(const MediumDev &m, d3 P, double nbar, d3 gbar, GradAcc &go) {
     const int nn[3] = {m.nx, m.ny, m.nz};
     int c[3];
     double f[3];
@@ -89,6 +137,7 @@ __device__ inline d3 grid_vjp(const MediumDev &m, d3 P, double nbar, d3 gbar, co
         f[a] = u - (double)ci;
     }
     double fbar[3] = {0.0, 0.0, 0.0};
+    go.open(c);
     for (int dz = 0; dz < 2; ++dz)
         for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
@@ -105,11 +154,11 @@ __device__ inline d3 grid_vjp(const MediumDev &m, d3 P, double nbar, d3 gbar, co
                 fbar[0] += (dx ? 1.0 : -1.0) * wy * wz * sv;
                 fbar[1] += (dy ? 1.0 : -1.0) * wx * wz * sv;
                 fbar[2] += (dz ? 1.0 : -1.0) * wx * wy * sv;
-                const size_t node = ((size_t)k * m.ny + j) * m.nx + i;
-                if (nbar != 0.0) grad_add(go.gv + node, w * nbar);
-                if (gbar.x != 0.0) grad_add(go.gH + node, w * gbar.x);
-                if (gbar.y != 0.0) grad_add(go.gH + go.nodes + node, w * gbar.y);
-                if (gbar.z != 0.0) grad_add(go.gH + 2 * go.nodes + node, w * gbar.z);
+                double *q = go.slot + (size_t)(4 * (dz * 4 + dy * 2 + dx)) * go.stride;
+                q[0] += w * nbar;
+                q[go.stride] += w * gbar.x;
+                q[2 * go.stride] += w * gbar.y;
+                q[3 * go.stride] += w * gbar.z;
             }
     return mk(inside[0] ? fbar[0] / m.h[0] : 0.0, inside[1] ? fbar[1] / m.h[1] : 0.0,
               inside[2] ? fbar[2] / m.h[2] : 0.0);
@@ -298,7 +347,7 @@ __device__ inline void surface_point_vjp(const BoundaryDev &b, d3 P, d3 R, doubl
 // the operation on entry, of the state before it on return.  (xbar, ybar):
 // adjoint of the exit-plane point, used when the operation is the exit.
 __device__ inline void vjp_op(const MediumDev &m, const BoundaryDev &b, const TraceDev &t,
-                              const St &s, Adj &a, double xbar, double ybar, const GradOut &go) {
+                              const St &s, Adj &a, double xbar, double ybar, GradAcc &go) {
     if (s.phase == PH_DECIDE) {
         double ni;
         d3 g;
@@ -388,7 +437,7 @@ __device__ inline void vjp_op(const MediumDev &m, const BoundaryDev &b, const Tr
 // VJP of the entry: the launch state is not differentiated, the node values
 // are (through n at the entry point).
 __device__ inline void vjp_entry(const MediumDev &m, const BoundaryDev &b, const TraceDev &t, d3 P0,
-                                 d3 d0, const Adj &a, const GradOut &go) {
+                                 d3 d0, const Adj &a, GradAcc &go) {
     const double l0 = sqrt(dot(d0, d0));
     const d3 I = mk(d0.x / l0, d0.y / l0, d0.z / l0);
     d3 P = P0;
