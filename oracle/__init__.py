@@ -23,7 +23,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 KINDS = {"homogeneous": 0, "linear": 1, "luneburg": 2, "fiber": 3, "gaussian": 4, "grid": 5,
-         "spherical": 6, "n2p": 7}
+         "spherical": 6, "n2p": 7, "zernike": 8}
 BOUNDARIES = {"box": 0, "sphere": 1, "cylinder": 2}
 
 EXITED, MISSED, TRUNCATED, NO_PLANE, INVALID_INPUT, REFLECTED_AT_ENTRY = range(6)

@@ -116,6 +116,53 @@ static void grid_eval(const orc_medium *m, const double P[3], double *n, double 
             }
 }
 
+/* Fringe Zernike polynomial j (1-based Fringe ordering; j <= 16) as
+ * (radial order n, azimuthal order m, cosine or sine). */
+static const int fringe_nm[17][3] = {
+    {0, 0, 0}, {0, 0, 0}, {1, 1, 0}, {1, 1, 1}, {2, 0, 0}, {2, 2, 0}, {2, 2, 1},
+    {3, 1, 0}, {3, 1, 1}, {4, 0, 0}, {3, 3, 0}, {3, 3, 1}, {4, 2, 0}, {4, 2, 1},
+    {5, 1, 0}, {5, 1, 1}, {6, 0, 0}};
+
+static double fact(int k) {
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= i;
+    return f;
+}
+
+/* Radial polynomial R_n^m(rho) = sum_k (-1)^k (n-k)! / (k! ((n+m)/2-k)! ((n-m)/2-k)!)
+ * rho^(n-2k), its derivative, and R / rho (m >= 1, a polynomial). */
+static void zernike_radial(int n, int m, double rho, double *R, double *dR, double *Rr) {
+    *R = *dR = *Rr = 0.0;
+    for (int k = 0; k <= (n - m) / 2; ++k) {
+        double c = ((k % 2) ? -1.0 : 1.0) * fact(n - k) /
+                   (fact(k) * fact((n + m) / 2 - k) * fact((n - m) / 2 - k));
+        int e = n - 2 * k;
+        *R += c * pow(rho, e);
+        if (e >= 1) *dR += c * e * pow(rho, e - 1);
+        if (e >= 1) *Rr += c * pow(rho, e - 1);
+    }
+}
+
+/* Legendre P_l(w) and P_l'(w) by the three-term recursion. */
+static void legendre(int l, double w, double *P, double *dP) {
+    double p0 = 1.0, p1 = w, d0 = 0.0, d1 = 1.0;
+    if (l == 0) {
+        *P = 1.0;
+        *dP = 0.0;
+        return;
+    }
+    for (int k = 1; k < l; ++k) {
+        double p2 = ((2 * k + 1) * w * p1 - k * p0) / (k + 1);
+        double d2 = d0 + (2 * k + 1) * p1;
+        p0 = p1;
+        p1 = p2;
+        d0 = d1;
+        d1 = d2;
+    }
+    *P = p1;
+    *dP = d1;
+}
+
 static void medium_eval(const orc_medium *m, const double P[3], double *n, double g[3]) {
     const double *p = m->params;
     switch (m->kind) {
@@ -207,6 +254,40 @@ static void medium_eval(const orc_medium *m, const double P[3], double *n, doubl
         double et[3] = {ct * cp, ct * sp, -st};
         double ep[3] = {-sp, cp, 0.0};
         for (int a = 0; a < 3; ++a) g[a] = dr * er[a] + dt * et[a] + dp * ep[a];
+        return;
+    }
+    case ORC_ZERNIKE: {
+        /* Sec. V: n = n0 + dn sum c_{j,l} Z_j(x', y') V_l(z'), x' = x / rho_max,
+         * y' = y / rho_max, z' = 2 z / z_max - 1, n0 = (n_hi + n_lo) / 2,
+         * dn = (n_hi - n_lo) / 2; Z_j Fringe Zernike polynomials in polar form
+         * R(rho) cos/sin(m theta), V_l Legendre polynomials. */
+        double nlo = p[0], nhi = p[1], rm = p[2], zm = p[3];
+        int K = (int)p[4];
+        double n0 = 0.5 * (nhi + nlo), dn = 0.5 * (nhi - nlo);
+        double u = P[0] / rm, v = P[1] / rm, w = 2.0 * P[2] / zm - 1.0;
+        double rho = sqrt(u * u + v * v), th = atan2(v, u);
+        double ct = cos(th), st = sin(th);
+        double nv = n0;
+        g[0] = g[1] = g[2] = 0.0;
+        for (int k = 0; k < K; ++k) {
+            int j = (int)p[5 + 3 * k], l = (int)p[6 + 3 * k];
+            double c = p[7 + 3 * k];
+            int rn = fringe_nm[j][0], am = fringe_nm[j][1], sn = fringe_nm[j][2];
+            double R, dR, Rr;
+            zernike_radial(rn, am, rho, &R, &dR, &Rr);
+            double T = am == 0 ? 1.0 : (sn ? sin(am * th) : cos(am * th));
+            double dT = am == 0 ? 0.0 : (sn ? am * cos(am * th) : -am * sin(am * th));
+            double Z = R * T;
+            double Zu = dR * ct * T - Rr * dT * st; /* d/du = cos d/drho - sin/rho d/dtheta */
+            double Zv = dR * st * T + Rr * dT * ct;
+            double V, dV;
+            legendre(l, w, &V, &dV);
+            nv += dn * c * Z * V;
+            g[0] += dn * c * Zu * V / rm;
+            g[1] += dn * c * Zv * V / rm;
+            g[2] += dn * c * Z * dV * 2.0 / zm;
+        }
+        *n = nv;
         return;
     }
     case ORC_N2P: {
@@ -722,10 +803,19 @@ static int check_medium(const orc_medium *m, const orc_params *q) {
     if (!(m->n_amb > 0.0)) return -1;
     if (m->kind == ORC_GRID) {
         if (!m->grid || m->nx < 2 || m->ny < 2 || m->nz < 2) return -1;
-    } else if (m->kind < 0 || m->kind > ORC_N2P || !m->params) {
+    } else if (m->kind < 0 || m->kind > ORC_ZERNIKE || !m->params) {
         return -1;
     } else if (m->kind == ORC_SPHERICAL && m->n_params != 7) {
         return -1;
+    } else if (m->kind == ORC_ZERNIKE) {
+        if (m->n_params < 5) return -1;
+        int K = (int)m->params[4];
+        if (K < 0 || m->n_params != 5 + 3 * K || !(m->params[2] > 0.0) || !(m->params[3] > 0.0))
+            return -1;
+        for (int k = 0; k < K; ++k) {
+            int j = (int)m->params[5 + 3 * k], l = (int)m->params[6 + 3 * k];
+            if (j < 1 || j > 16 || l < 0 || l > 3) return -1;
+        }
     } else if (m->kind == ORC_N2P &&
                (m->n_params != 4 || !(m->params[0] > 0.0) || !(m->params[1] > 0.0))) {
         return -1;

@@ -29,7 +29,9 @@ enum {
     ORC_GAUSSIAN = 4,    /* params [n0, K, (A, sigma, cx, cy, cz) x K]            */
     ORC_GRID = 5,        /* trilinear grid, node-central-difference gradient      */
     ORC_SPHERICAL = 6,   /* params [a0, a1, a2, a3, cx, cy, cz]  Sec. V, Eq. (26) */
-    ORC_N2P = 7          /* params [R, F, beta, gamma]  Sec. VI, Eq. (27), axis z */
+    ORC_N2P = 7,         /* params [R, F, beta, gamma]  Sec. VI, Eq. (27), axis z */
+    ORC_ZERNIKE = 8      /* params [n_lo, n_hi, rho_max, z_max, K, (j, l, c) x K]
+                          * Sec. V: Fringe Zernike j <= 16 times Legendre l <= 3 */
 };
 
 /* boundary kinds (convex enclosing surface, Sec. II case (i)) */

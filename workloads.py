@@ -13,7 +13,7 @@ them as float64).
 Media are plain dicts::
 
     {"kind": "luneburg" | "gaussian" | "linear" | "homogeneous" | "fiber" | "grid" |
-             "spherical" | "n2p",
+             "spherical" | "n2p" | "zernike",
      "params": float64 array (layout per kind, see ``MEDIUM_PARAM_LAYOUT``),
      "boundary": {"kind": "box" | "sphere" | "cylinder", "params": float64 array},
      "n_amb": float,
@@ -41,6 +41,8 @@ MEDIUM_PARAM_LAYOUT = {
     "grid": "[] (values in 'grid', nodes spanning grid_lo..grid_hi)",
     "spherical": "[a0, a1, a2, a3, cx, cy, cz]  Sec. V, Eq. (26) about (cx, cy, cz)",
     "n2p": "[R, F, beta, gamma]          Sec. VI, Eq. (27), axis z; lens = cylinder boundary",
+    "zernike": "[n_lo, n_hi, rho_max, z_max, K, (j, l, c) x K]  Sec. V, Fringe Zernike j <= 16, "
+               "Legendre l <= 3",
 }
 BOUNDARY_PARAM_LAYOUT = {
     "box": "[lox, loy, loz, hix, hiy, hiz]",
@@ -255,6 +257,43 @@ def sphere_aimed_rays(n_rays, seed, r_launch=1.5, r_target=0.8):
     T = (r_target * np.cbrt(u[:, 2]))[:, None] * unit(1.0 - 2.0 * u[:, 3], 2.0 * math.pi * u[:, 4])
     d0 = T - P0
     d0 /= np.linalg.norm(d0, axis=1)[:, None]
+    return _f32(P0), _f32(d0)
+
+
+# Sec. V: the corrective freeform cylindrical lens, Fringe Zernike x Legendre
+ZERNIKE_TERMS = ((5, 0, -0.2368), (8, 0, 0.0249), (9, 0, 0.0011), (11, 0, -0.0078),
+                 (12, 0, -0.0013), (8, 1, 0.5548), (11, 1, -0.1731))
+
+
+def zernike_lens(n_lo=1.5261, n_hi=1.5608, rho_max=4.2, z_max=2.5, terms=ZERNIKE_TERMS):
+    """n = n0 + dn sum c Z_j(x/rho_max, y/rho_max) V_l(2z/z_max - 1) in the
+    cylinder rho <= rho_max, 0 <= z <= z_max, in air (the paper's coefficients
+    and geometry)."""
+    t = np.asarray(terms, dtype=np.float64).ravel()
+    return {"kind": "zernike",
+            "params": np.concatenate([[n_lo, n_hi, rho_max, z_max, len(terms)], t]),
+            "boundary": {"kind": "cylinder", "params": np.array([0.0, 0.0, rho_max, 0.0, z_max])},
+            "n_amb": 1.0}
+
+
+def zernike_rays(n_rays, seed, rho_max=4.2, z_max=2.5):
+    """The paper's launch of Fig. 3(a) -- P0 = (1, -5, -1.5), theta0 = 80 deg,
+    phi0 = 110 deg -- followed by n_rays - 1 rays from the plane z = -0.5
+    (uniform in the disc of radius rho_max) to points uniform in the lens
+    volume.  One draw u ~ U[0,1) of shape (n_rays, 5).  Rounded to float32."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((n_rays, 5))
+    r0 = rho_max * np.sqrt(u[:, 0])
+    a0 = 2 * math.pi * u[:, 1]
+    P0 = np.stack([r0 * np.cos(a0), r0 * np.sin(a0), np.full(n_rays, -0.5)], axis=1)
+    r1 = 0.95 * rho_max * np.sqrt(u[:, 2])
+    a1 = 2 * math.pi * u[:, 3]
+    T = np.stack([r1 * np.cos(a1), r1 * np.sin(a1), z_max * u[:, 4]], axis=1)
+    d0 = T - P0
+    d0 /= np.linalg.norm(d0, axis=1)[:, None]
+    th, ph = math.radians(80.0), math.radians(110.0)
+    P0[0] = (1.0, -5.0, -1.5)
+    d0[0] = (math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th))
     return _f32(P0), _f32(d0)
 
 
