@@ -68,10 +68,19 @@ enum vrt_medium_kind {
                                  * freeform n = a0 + a1 G1 + a2 G2 + a3 G3 about c,
                                  * G1 = 0.3 (r^2 - 1), G2 = r cos(5 theta), G3 = r^2 sin^2(theta)
                                  * cos(2 phi); the gradient is undefined at r = 0 (case (ii)) */
-    VRT_MEDIUM_N2P = 7          /* params [R, F, beta, gamma]  Sec. VI, Eq. (27): cylindrical N2P
+    VRT_MEDIUM_N2P = 7,         /* params [R, F, beta, gamma]  Sec. VI, Eq. (27): cylindrical N2P
                                  * lens n = [1 + ((R^2 - (rho/2)^2) / F^2)^beta]^gamma, rho the
                                  * distance from the z axis; the lens volume is the boundary
                                  * (cylinder 0 <= rho <= R), n_ambient the surroundings (1) */
+    VRT_MEDIUM_ZERNIKE = 8      /* params [n_lo, n_hi, rho_max, z_max, K, (j, l, c) x K]  Sec. V:
+                                 * freeform cylindrical lens n = n0 + dn sum c Z_j(x', y') V_l(z'),
+                                 * n0 = (n_hi + n_lo)/2, dn = (n_hi - n_lo)/2, x' = x/rho_max,
+                                 * y' = y/rho_max, z' = 2z/z_max - 1; Z_j the Fringe Zernike
+                                 * polynomial j (1..16, unnormalised: Z4 = 2 rho^2 - 1,
+                                 * Z5 = rho^2 cos 2theta, ...), V_l the Legendre polynomial
+                                 * l (0..3); repeated (j, l) pairs add; K <= 64.  The lens
+                                 * volume is the boundary (normally the cylinder rho <= rho_max,
+                                 * 0 <= z <= z_max) */
 };
 #define VRT_MAX_BUMPS 64
 

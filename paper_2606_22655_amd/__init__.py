@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libvrt.so")
 
 VRT_OK, VRT_EINVAL, VRT_ENOMEM, VRT_EHIP, VRT_EUNSUPPORTED, VRT_ETIMEOUT = 0, -1, -2, -3, -4, -5
 MEDIUM_KINDS = {"homogeneous": 0, "linear": 1, "luneburg": 2, "fiber": 3, "gaussian": 4, "grid": 5,
-                "spherical": 6, "n2p": 7}
+                "spherical": 6, "n2p": 7, "zernike": 8}
 BOUNDARY_KINDS = {"box": 0, "sphere": 1, "cylinder": 2}
 VRT_FP64, VRT_FP32_COMP = 0, 1
 PRECISIONS = {"fp64": VRT_FP64, "fp32c": VRT_FP32_COMP}

@@ -13,7 +13,9 @@
 // Precision plan:
 //   - n and grad n in single precision; the index difference to the previous
 //     point is formed from the move vector (media.h), so mu_i - 1 keeps full
-//     relative precision;
+//     relative precision.  Media whose index is taken in double (kIndexIn64)
+//     are evaluated once per step at the compensated position, and n(P_{i-1})
+//     is kept in double, so dn is the difference of two double indices;
 //   - Snell is applied as an increment R - I = (mu-1) I + gamma N with
 //     gamma = -sgn(c) (mu-1)(mu+1) / (sqrt(D) + mu |c|), the same root as
 //     Eq. (10) without its cancellation;
@@ -62,7 +64,8 @@ struct Lane {
     float Ihx, Ihy, Ihz, Icx, Icy, Icz;  // direction I = Ih - Ic
     float sx, sy, sz;                    // last move P_i - P_{i-1}
     float nlb;                           // n(P_{i-1}) = nlb + nld (grid: cell base value
-    double nld;                          //   + offset inside the cell; analytic: nld = 0)
+    double nld;                          //   + offset inside the cell; media taken in double:
+                                         //   the double index split; other media: nld = 0)
     float Delta;                         // pending move length
     uint32_t r, steps, ntir, nbtir, flags;
     bool pending;                        // R = I and Delta set by an event: move without deciding
@@ -217,6 +220,10 @@ __device__ __forceinline__ void index_at_event(const MediumDev &m, const float4 
         split(P.y, phy, pcy);
         split(P.z, phz, pcz);
         grid32(m, rec, gc, phx, phy, phz, pcx, pcy, pcz, 0.f, 0.0, n, nlb, nld, gx, gy, gz, dn);
+    } else if constexpr (kIndexIn64<MK>) {
+        const double n = index64<MK>(m, P);
+        nlb = (float)n;
+        nld = n - (double)nlb;
     } else {
         nlb = (float)index64<MK>(m, P);
         nld = 0.0;
@@ -291,11 +298,25 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
     if (!L.pending) {
         float ni, gx, gy, gz, dn, nb = 0.f;
         double nd = 0.0;
-        float n_last = L.nlb;  // analytic media keep nld = 0
+        float n_last = L.nlb;  // float-evaluated analytic media keep nld = 0
         if constexpr (MK == VRT_MEDIUM_GRID) n_last = (float)((double)L.nlb + L.nld);
         if constexpr (MK == VRT_MEDIUM_GRID) {
             grid32(m, rec, gc, L.Phx, L.Phy, L.Phz, L.Pcx, L.Pcy, L.Pcz, L.nlb, L.nld, ni, nb, nd, gx,
                    gy, gz, dn);
+        } else if constexpr (kIndexIn64<MK>) {
+            // n and grad n in double at the compensated position; n(P_{i-1}) is
+            // kept as nlb + nld, so dn is a difference of two double indices
+            const d3 P64 = mk((double)L.Phx - L.Pcx, (double)L.Phy - L.Pcy, (double)L.Phz - L.Pcz);
+            double n64;
+            d3 g64;
+            med64<MK>(m, P64, n64, g64);
+            ni = nb = (float)n64;
+            nd = n64 - (double)nb;
+            dn = (float)(n64 - ((double)L.nlb + L.nld));
+            gx = (float)g64.x;
+            gy = (float)g64.y;
+            gz = (float)g64.z;
+            (void)n_last;
         } else {
             f3 g;
             med32<MK>(m, mf, bumps, dL0, mkf(L.Phx, L.Phy, L.Phz), mkf(L.sx, L.sy, L.sz), n_last,
@@ -327,6 +348,14 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
                     GridCache g2 = gc;
                     grid32(m, rec, g2, L.Phx + qx, L.Phy + qy, L.Phz + qz, L.Pcx, L.Pcy, L.Pcz, nb, nd, np,
                            pb, pd, px, py, pz, dnp);
+                } else if constexpr (kIndexIn64<MK>) {
+                    const d3 Q64 = mk((double)L.Phx - L.Pcx + qx, (double)L.Phy - L.Pcy + qy,
+                                      (double)L.Phz - L.Pcz + qz);
+                    double nq;
+                    d3 gq;
+                    med64<MK>(m, Q64, nq, gq);
+                    np = (float)nq;
+                    dnp = (float)(nq - ((double)nb + nd));
                 } else {
                     f3 gp;
                     med32<MK>(m, mf, bumps, dL0, mkf(L.Phx + qx, L.Phy + qy, L.Phz + qz), mkf(qx, qy, qz), ni,
@@ -400,7 +429,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
             }
         }
         L.nlb = nb;
-        if constexpr (MK == VRT_MEDIUM_GRID) L.nld = nd;
+        if constexpr (MK == VRT_MEDIUM_GRID || kIndexIn64<MK>) L.nld = nd;
         kahan_add(L.Ihx, L.Icx, incx);
         kahan_add(L.Ihy, L.Icy, incy);
         kahan_add(L.Ihz, L.Icz, incz);

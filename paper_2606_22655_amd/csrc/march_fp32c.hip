@@ -16,7 +16,7 @@ struct Launch32 {
 };
 
 template <int MK>
-__global__ __launch_bounds__(256, MK == VRT_MEDIUM_GRID ? 2 : 3) void march_fp32c_kernel(
+__global__ __launch_bounds__(256, MK == VRT_MEDIUM_GRID || MK == VRT_MEDIUM_ZERNIKE ? 2 : 3) void march_fp32c_kernel(
     Launch32 desc, const float *__restrict__ bumps, const float4 *__restrict__ rec, uint32_t n,
     uint32_t *queue) {
     const Launch32 *__restrict__ D = &desc;
@@ -102,6 +102,7 @@ hipError_t launch_march_fp32c(const LaunchArgs &a) {
     case VRT_MEDIUM_GRID: return launch32<VRT_MEDIUM_GRID>(a);
     case VRT_MEDIUM_SPHERICAL: return launch32<VRT_MEDIUM_SPHERICAL>(a);
     case VRT_MEDIUM_N2P: return launch32<VRT_MEDIUM_N2P>(a);
+    case VRT_MEDIUM_ZERNIKE: return launch32<VRT_MEDIUM_ZERNIKE>(a);
     }
     return hipErrorInvalidValue;
 }

@@ -54,6 +54,7 @@ hipError_t launch_march_fp64(const LaunchArgs &a) {
     case VRT_MEDIUM_GRID: return launch64<VRT_MEDIUM_GRID>(a);
     case VRT_MEDIUM_SPHERICAL: return launch64<VRT_MEDIUM_SPHERICAL>(a);
     case VRT_MEDIUM_N2P: return launch64<VRT_MEDIUM_N2P>(a);
+    case VRT_MEDIUM_ZERNIKE: return launch64<VRT_MEDIUM_ZERNIKE>(a);
     }
     return hipErrorInvalidValue;
 }

@@ -20,6 +20,9 @@
 //   HOMOGENEOUS [n]  LINEAR [n0, gx, gy, gz]  LUNEBURG [R, cx, cy, cz]
 //   FIBER [n_c, Delta, R, cx, cy]  GAUSSIAN [n0] + bumps_d (A, sigma, cx, cy, cz) x K
 //   SPHERICAL [a0, a1, a2, a3, cx, cy, cz]  N2P [R, F, beta, gamma]
+//   ZERNIKE [n0, dn, rho_max, z_max] + bumps_d = c[j - 1][l] (16 x 4, row j - 1 of
+//           Fringe term j, column l of Legendre polynomial l), K = mask of the
+//           rows that hold a nonzero coefficient
 // MedF.q holds single-precision derived constants (see vrt_api.hip).
 // Discretized media keep the node values and node records
 // (n, h_x, h_y, h_z) where h_a is the central difference of the node values
@@ -74,6 +77,61 @@ __device__ inline void grid_cell64(const MediumDev &m, d3 P, int c[3], double f[
         ci = ci < 0 ? 0 : (ci > nn[a] - 2 ? nn[a] - 2 : ci);
         c[a] = ci;
         f[a] = u - (double)ci;
+    }
+}
+
+// Fringe Zernike polynomial j (1..16, unnormalised) at (u, v) in Cartesian form,
+// with its partial derivatives.  r2 = u^2 + v^2.
+__device__ __forceinline__ void fringe64(int j, double u, double v, double &Z, double &Zu,
+                                         double &Zv) {
+    const double r2 = u * u + v * v;
+    switch (j) {
+    case 1: Z = 1.0; Zu = 0.0; Zv = 0.0; break;
+    case 2: Z = u; Zu = 1.0; Zv = 0.0; break;
+    case 3: Z = v; Zu = 0.0; Zv = 1.0; break;
+    case 4: Z = 2.0 * r2 - 1.0; Zu = 4.0 * u; Zv = 4.0 * v; break;
+    case 5: Z = u * u - v * v; Zu = 2.0 * u; Zv = -2.0 * v; break;
+    case 6: Z = 2.0 * u * v; Zu = 2.0 * v; Zv = 2.0 * u; break;
+    case 7: Z = (3.0 * r2 - 2.0) * u; Zu = 3.0 * r2 - 2.0 + 6.0 * u * u; Zv = 6.0 * u * v; break;
+    case 8: Z = (3.0 * r2 - 2.0) * v; Zu = 6.0 * u * v; Zv = 3.0 * r2 - 2.0 + 6.0 * v * v; break;
+    case 9: {
+        Z = (6.0 * r2 - 6.0) * r2 + 1.0;
+        const double d = 24.0 * r2 - 12.0;  // dZ/du = d u
+        Zu = d * u;
+        Zv = d * v;
+        break;
+    }
+    case 10: Z = u * u * u - 3.0 * u * v * v; Zu = 3.0 * (u * u - v * v); Zv = -6.0 * u * v; break;
+    case 11: Z = 3.0 * u * u * v - v * v * v; Zu = 6.0 * u * v; Zv = 3.0 * (u * u - v * v); break;
+    case 12: {
+        const double a = 4.0 * r2 - 3.0, b = u * u - v * v;
+        Z = a * b;
+        Zu = 8.0 * u * b + 2.0 * a * u;
+        Zv = 8.0 * v * b - 2.0 * a * v;
+        break;
+    }
+    case 13: {
+        const double a = 4.0 * r2 - 3.0, b = 2.0 * u * v;
+        Z = a * b;
+        Zu = 8.0 * u * b + 2.0 * a * v;
+        Zv = 8.0 * v * b + 2.0 * a * u;
+        break;
+    }
+    case 14: case 15: {
+        const double a = (10.0 * r2 - 12.0) * r2 + 3.0, da = 40.0 * r2 - 24.0;  // da = 2 a'(r2)
+        const double t = j == 14 ? u : v;
+        Z = a * t;
+        Zu = da * u * t + (j == 14 ? a : 0.0);
+        Zv = da * v * t + (j == 15 ? a : 0.0);
+        break;
+    }
+    default: {  // 16
+        Z = ((20.0 * r2 - 30.0) * r2 + 12.0) * r2 - 1.0;
+        const double d = (120.0 * r2 - 120.0) * r2 + 24.0;  // 2 dZ/d(r2)
+        Zu = d * u;
+        Zv = d * v;
+        break;
+    }
     }
 }
 
@@ -151,6 +209,31 @@ __device__ inline void med64(const MediumDev &m, d3 P, double &n, d3 &g) {
         n = pow(u, ga);
         const double k = 2.0 * (ga * (n / u) * be * (wb / w) * (-1.0 / (4.0 * F * F)));
         g = mk(k * P.x, k * P.y, 0.0);
+    } else if constexpr (MK == VRT_MEDIUM_ZERNIKE) {
+        // Sec. V: n = n0 + dn sum_j Z_j(u, v) A_j(w) with u = x / rho_max,
+        // v = y / rho_max, w = 2 z / z_max - 1 and A_j(w) = sum_l c[j][l] P_l(w)
+        // (Legendre P0..P3); the chain rule scales d/du, d/dv by 1 / rho_max and
+        // d/dw by 2 / z_max.
+        const double n0 = p[0], dn = p[1], rm = p[2], zm = p[3];
+        const double u = P.x / rm, v = P.y / rm, w = 2.0 * P.z / zm - 1.0;
+        const double L1 = w, L2 = (3.0 * w * w - 1.0) / 2.0, L3 = (5.0 * w * w - 3.0) * w / 2.0;
+        const double dL2 = 3.0 * w, dL3 = (15.0 * w * w - 3.0) / 2.0;
+        double s = 0.0, su = 0.0, sv = 0.0, sw = 0.0;
+#pragma unroll
+        for (int j = 1; j <= 16; ++j) {  // unrolled: each term's form is fixed at compile time
+            if (!((m.K >> (j - 1)) & 1)) continue;
+            const double *c = m.bumps_d + 4 * (j - 1);
+            const double A = c[0] + c[1] * L1 + c[2] * L2 + c[3] * L3;
+            const double dA = c[1] + c[2] * dL2 + c[3] * dL3;
+            double Z, Zu, Zv;
+            fringe64(j, u, v, Z, Zu, Zv);
+            s += Z * A;
+            su += Zu * A;
+            sv += Zv * A;
+            sw += Z * dA;
+        }
+        n = n0 + dn * s;
+        g = mk(dn * su / rm, dn * sv / rm, dn * sw * 2.0 / zm);
     } else {  // GRID: trilinear n, trilinear node central differences
         int c[3];
         double f[3];
@@ -205,6 +288,14 @@ constexpr double kGaussRhoMax = 5e-2;
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Media whose index the single-precision march takes in double (their terms
+// span several orders of magnitude or need pow): the march evaluates med64 at
+// the compensated position once per step and keeps n(P_{i-1}) in double, so
+// the index difference is the difference of two double indices (lane32.h).
+template <int MK>
+constexpr bool kIndexIn64 =
+    MK == VRT_MEDIUM_SPHERICAL || MK == VRT_MEDIUM_N2P || MK == VRT_MEDIUM_ZERNIKE;
+
 // P: point P_i, s = P_i - P_{i-1}, n_last = n(P_{i-1}).  bumps: the Gaussian
 // table (m.bumps_f) -- a restrict kernel argument in the batch kernel (its
 // loads are then scalar), a copy in LDS in the serving kernel.
@@ -214,6 +305,7 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 template <int MK, class BumpPtr>
 __device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf, BumpPtr bumps, float dL0,
                                       f3 P, f3 s, float n_last, float &n, f3 &g, float &dn) {
+    static_assert(!kIndexIn64<MK>, "index taken in double by the march");
     if constexpr (MK == VRT_MEDIUM_HOMOGENEOUS) {
         n = mf.q[0];
         g = mkf(0, 0, 0);
@@ -252,20 +344,6 @@ __device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf, BumpPt
         } else {
             dn = n - n_last;
         }
-    } else if constexpr (MK == VRT_MEDIUM_SPHERICAL || MK == VRT_MEDIUM_N2P) {
-        // evaluated in double: n, grad n at P_i and the index difference as the
-        // difference of the double indices at P_i and P_i - s (error ~1e-16,
-        // far below the single-precision step)
-        const d3 P64 = mk((double)P.x, (double)P.y, (double)P.z);
-        const d3 Pp64 = mk(P64.x - (double)s.x, P64.y - (double)s.y, P64.z - (double)s.z);
-        double n64, np64;
-        d3 g64, gp64;
-        med64<MK>(m, P64, n64, g64);
-        med64<MK>(m, Pp64, np64, gp64);
-        n = (float)n64;
-        g = mkf((float)g64.x, (float)g64.y, (float)g64.z);
-        dn = (float)(n64 - np64);
-        (void)n_last;
     } else if constexpr (MK == VRT_MEDIUM_GAUSSIAN) {
         // E_k(P_{i-1}) = E_k(P_i) exp(dq_k), dq_k = ((P_i - c_k).s - |s|^2/2) / sigma^2,
         // so n_i - n_{i-1} = -sum A_k E_k(P_i) expm1(dq_k), with A_k expm1 as a

@@ -482,6 +482,7 @@ __global__ __launch_bounds__(256, kServeOcc) void serve_kernel(const JobDesc *hd
             case VRT_MEDIUM_GAUSSIAN: march_group<VRT_MEDIUM_GAUSSIAN>(c, Dl, B, group); break;
             case VRT_MEDIUM_SPHERICAL: march_group<VRT_MEDIUM_SPHERICAL>(c, Dl, B, group); break;
             case VRT_MEDIUM_N2P: march_group<VRT_MEDIUM_N2P>(c, Dl, B, group); break;
+            case VRT_MEDIUM_ZERNIKE: march_group<VRT_MEDIUM_ZERNIKE>(c, Dl, B, group); break;
             default: march_group<VRT_MEDIUM_GRID>(c, Dl, B, group); break;
             }
             idle = 0;

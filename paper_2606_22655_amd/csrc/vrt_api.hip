@@ -207,11 +207,11 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
         return fail(VRT_EINVAL, "vrt_medium_create_analytic: params missing or non-finite");
     if (!(n_ambient > 0.0) || !isfinite(n_ambient))
         return fail(VRT_EINVAL, "n_ambient must be finite and > 0");
-    static const int need[] = {1, 4, 4, 5, -1, -1, 7, 4};
-    if (kind < VRT_MEDIUM_HOMOGENEOUS || kind > VRT_MEDIUM_N2P || kind == VRT_MEDIUM_GRID)
+    static const int need[] = {1, 4, 4, 5, -1, -1, 7, 4, -1};
+    if (kind < VRT_MEDIUM_HOMOGENEOUS || kind > VRT_MEDIUM_ZERNIKE || kind == VRT_MEDIUM_GRID)
         return fail(VRT_EINVAL, "analytic medium kind %d unknown (grids use vrt_medium_create_grid)",
                     kind);
-    if (kind != VRT_MEDIUM_GAUSSIAN && n_params != need[kind])
+    if (need[kind] >= 0 && n_params != need[kind])
         return fail(VRT_EINVAL, "medium kind %d needs %d params, got %d", kind, need[kind], n_params);
     BoundaryDev b;
     if (int rc = check_boundary(bnd, b)) return rc;
@@ -279,6 +279,52 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
         }
         for (int i = 0; i < 4; ++i) d.q[i] = p[i];
         break;
+    case VRT_MEDIUM_ZERNIKE: {
+        // Sec. V; the terms are folded into a 16 x 4 table c[j - 1][l] (media.h)
+        const int K = n_params >= 5 ? (int)p[4] : -1;
+        if (n_params < 5 || (double)K != p[4] || K < 0 || K > 64 || n_params != 5 + 3 * K) {
+            delete m;
+            return fail(VRT_EINVAL, "zernike medium: [n_lo, n_hi, rho_max, z_max, K, (j, l, c) x K], "
+                                    "K in [0, 64]");
+        }
+        if (!(p[2] > 0.0) || !(p[3] > 0.0)) {
+            delete m;
+            return fail(VRT_EINVAL, "zernike medium: rho_max and z_max must be > 0");
+        }
+        std::vector<double> tab(64, 0.0);
+        int mask = 0;
+        for (int k = 0; k < K; ++k) {
+            const double *t = p + 5 + 3 * k;
+            const int j = (int)t[0], l = (int)t[1];
+            if ((double)j != t[0] || (double)l != t[1] || j < 1 || j > 16 || l < 0 || l > 3) {
+                delete m;
+                return fail(VRT_EINVAL, "zernike term %d: Fringe index j in [1, 16] and Legendre "
+                                        "order l in [0, 3]", k);
+            }
+            tab[4 * (j - 1) + l] += t[2];
+        }
+        for (int j = 0; j < 16; ++j)
+            if (tab[4 * j] != 0.0 || tab[4 * j + 1] != 0.0 || tab[4 * j + 2] != 0.0 ||
+                tab[4 * j + 3] != 0.0)
+                mask |= 1 << j;
+        d.q[0] = 0.5 * (p[1] + p[0]);
+        d.q[1] = 0.5 * (p[1] - p[0]);
+        d.q[2] = p[2];
+        d.q[3] = p[3];
+        d.K = mask;
+        void *pd = nullptr;
+        if ((rc = dev_alloc(m, &pd, tab.size() * sizeof(double)))) {
+            free_medium(m);
+            return rc;
+        }
+        hipError_t e = hipMemcpy(pd, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_medium(m);
+            return fail_hip(e, "hipMemcpy (zernike coefficients)");
+        }
+        d.bumps_d = (const double *)pd;
+        break;
+    }
     case VRT_MEDIUM_GAUSSIAN: {
         if (n_params < 2) {
             delete m;

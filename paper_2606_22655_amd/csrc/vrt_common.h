@@ -48,10 +48,10 @@ __host__ __device__ inline void fill_bump_f(const double *q, float *o) {
 
 struct MediumDev {
     int kind;        // vrt_medium_kind
-    int K;           // bumps (GAUSSIAN)
+    int K;           // bumps (GAUSSIAN); mask of the Fringe terms present (ZERNIKE)
     double n_amb;    // surroundings
     double q[8];     // analytic parameters as given (layout in media.h)
-    const double *bumps_d;  // K * kBumpD (GAUSSIAN)
+    const double *bumps_d;  // K * kBumpD (GAUSSIAN); 16 x 4 coefficient table (ZERNIKE)
     const float *bumps_f;   // K * kBumpF (GAUSSIAN)
     // discretized medium
     const float *grid;      // nz*ny*nx node values, x fastest

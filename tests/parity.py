@@ -209,19 +209,34 @@ def assert_stats(rep, z_max=4.5):
     assert rep["chi2"] <= dof + 5.0 * math.sqrt(2.0 * dof), rep
 
 
-def ill_conditioned(orc_trace, spec, rays, params, delta=1e-9, tol=1e-5):
+def ill_conditioned(orc_trace, spec, rays, params, delta=1e-9, tol=1e-5, turn=0.0):
     """Rays whose oracle result is itself unstable: shifting the launch point
-    by delta (x and y) changes the event counts or moves the exit state by
-    more than tol.  Returns a boolean mask."""
+    by delta (x and y) -- or, with turn > 0, turning the launch direction by
+    turn radians -- changes the event counts or moves the exit state by more
+    than tol.  Returns a boolean mask."""
     o = orc_trace(spec, rays, params)
+
+    def unstable(o2):
+        return ((o["status"] != o2["status"]) | (o["ntir"] != o2["ntir"]) |
+                (o["nbtir"] != o2["nbtir"]) |
+                (np.linalg.norm(o["P"] - o2["P"], axis=1) > tol) |
+                (angle_between(o["D"], o2["D"]) > tol))
+
     P = rays[0].copy()
     P[:, 0] += delta
     P[:, 1] -= delta
-    o2 = orc_trace(spec, (P, rays[1]), params)
-    return ((o["status"] != o2["status"]) | (o["ntir"] != o2["ntir"]) |
-            (o["nbtir"] != o2["nbtir"]) |
-            (np.linalg.norm(o["P"] - o2["P"], axis=1) > tol) |
-            (angle_between(o["D"], o2["D"]) > tol))
+    bad = unstable(orc_trace(spec, (P, rays[1]), params))
+    if turn > 0.0:
+        # a unit vector across each direction (a fixed oblique axis crossed with D)
+        D = rays[1]
+        t = np.cross(D, np.array([0.3, 0.5, 0.81]))
+        ln = np.linalg.norm(t, axis=1)
+        t[ln < 1e-3] = np.cross(D[ln < 1e-3], np.array([1.0, 0.0, 0.0]))
+        t /= np.linalg.norm(t, axis=1)[:, None]
+        D2 = D + turn * t
+        D2 /= np.linalg.norm(D2, axis=1)[:, None]
+        bad |= unstable(orc_trace(spec, (rays[0], D2), params))
+    return bad
 
 
 def exempt(rep_input, mask):

@@ -36,8 +36,9 @@ def ctx(vrt):
 
 @pytest.fixture(scope="module")
 def media(vrt, ctx):
-    """Seven media: Gaussian-bump cube, 48^3 quantized grid, Luneburg sphere,
-    fiber cylinder, linear slab, spherical freeform sphere, N2P lens."""
+    """Eight media: Gaussian-bump cube, 48^3 quantized grid, Luneburg sphere,
+    fiber cylinder, linear slab, spherical freeform sphere, N2P lens,
+    Zernike-Legendre lens."""
     specs = [workloads.gaussian_medium(500), workloads.grid_medium(workloads.noise_grid(48, 504))]
     lun, _, _ = workloads.luneburg_beam(n_side=4)
     specs.append(lun)
@@ -49,6 +50,7 @@ def media(vrt, ctx):
                   "n_amb": 1.0})
     specs.append(workloads.spherical_medium())
     specs.append(workloads.n2p_lens(0.6791, 5.0069, 0.2))
+    specs.append(workloads.zernike_lens())
     meds = [vrt.Medium(ctx, s) for s in specs]
     yield specs, meds
     for m in meds:
@@ -62,6 +64,8 @@ def job_rays(spec, n, seed):
         return workloads.face_cone_rays(n, seed, 25.0)
     if spec["kind"] == "spherical":  # aimed into the ball from outside
         return workloads.sphere_aimed_rays(n, seed)
+    if spec["kind"] == "zernike":  # from below the lens to points inside it
+        return workloads.zernike_rays(n, seed)
     rng = np.random.default_rng(seed)
     if spec["kind"] == "n2p":  # parallel rays onto the lens face
         r = 0.95 * np.sqrt(rng.uniform(0.0, 1.0, n))
@@ -132,19 +136,23 @@ def test_served_results_meet_the_parity_bar(vrt, ctx, media):
 
     specs, meds = media
     jobs = mixed_jobs(specs, 2, [3000, 2000, 4000, 1500, 2500, 3500])
+    zi = [s["kind"] for s in specs].index("zernike")
+    jobs.append((zi, job_rays(specs[zi], 1800, 77), params_for(specs[zi])))
     res, _, _ = serve_all(vrt, ctx, meds, jobs)
     for (mi, rays, prm), r in zip(jobs, res):
         o = oracle.trace(specs[mi], rays, prm)
         if specs[mi]["kind"] == "grid":  # chaotic medium: identical only for short marches
             continue
-        if specs[mi]["kind"] == "spherical":
-            # repeated TIR in the sphere: leave out the rays whose oracle result
-            # moves by 1e-5 under a float32-sized (1e-7) launch shift
-            bad = ill_conditioned(oracle.trace, specs[mi], rays, prm, delta=1e-7, tol=1e-5)
+        if specs[mi]["kind"] in ("spherical", "zernike"):
+            # repeated TIR in the sphere or along the lens wall: leave out the
+            # rays whose oracle result moves by 1e-5 under a float32-sized
+            # (1e-7) shift of the launch point or turn of the launch direction
+            bad = ill_conditioned(oracle.trace, specs[mi], rays, prm, delta=1e-7, tol=1e-5,
+                                  turn=1e-7)
             assert bad.sum() <= 0.10 * len(bad)
             o, r = exempt(o, bad), exempt(r, bad)
         ap = 2.0 if specs[mi]["boundary"]["kind"] == "sphere" else (
-            10.0 if specs[mi]["kind"] == "fiber" else 1.0)
+            10.0 if specs[mi]["kind"] == "fiber" else 4.2 if specs[mi]["kind"] == "zernike" else 1.0)
         assert_parity(compare(o, r, aperture=ap, spec=specs[mi]))
 
 
