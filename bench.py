@@ -2,7 +2,8 @@
 """Benchmark of the constant-OPL vectorial ray march on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload freeform|grid|luneburg|zernike|spherical|served|n2p|adjoint]
+                    [--workload freeform|grid|luneburg|zernike|spherical|helix|served|n2p|
+                                adjoint]
 
 A "step" of this benchmark is one pass of the whole hot path over one batch:
 one vrt_trace call that launches, enters, marches (medium evaluation, normal,
@@ -516,14 +517,105 @@ def adjoint_bench(vrt, torch, args):
     return out
 
 
+# ---------------------------------------------------------------------------
+# the paper's helix (Sec. IV): one ray, its polyline recorded
+# ---------------------------------------------------------------------------
+HELIX_FLOPS_PER_STEP = 15 + 50  # fiber index and gradient 15 (rho^2 3, n 5, slope 4, gradient 3)
+
+
+def helix_rays(P0, d0, n):
+    """n copies of the helix launch turned about the fiber axis by 2 pi k / n:
+    the fiber is axisymmetric, so each is the same helix, phase-shifted."""
+    a = 2.0 * math.pi * np.arange(n) / n
+    c, s = np.cos(a), np.sin(a)
+    rot = lambda v: np.stack([c * v[0] - s * v[1], s * v[0] + c * v[1], np.full(n, v[2])], axis=1)
+    return rot(P0[0]), rot(d0[0])
+
+
+def helix_bench(vrt, torch, args, n_batch=196608):
+    """The helical ray of Sec. IV at dL0 = 1e-4 (808,360 steps).  Timed step:
+    a batch of 196,608 copies of the helix (turned about the axis; 3 waves per
+    SIMD, the FP64 kernel's occupancy) on the plain FP64 march.  Beside it,
+    the paper's single ray with its polyline recorded (vrt_trace_paths): one
+    ray is one lane, so that figure is a latency."""
+    spec, (P0, d0), hx = workloads.helix_fiber()
+    prm = {"dL0": 1e-4, "max_steps": 2_000_000}
+    ctx = vrt.Context(0)
+    med = vrt.Medium(ctx, spec)
+    stream = torch.cuda.current_stream()
+    # batch of helices, plain FP64 march
+    rays = helix_rays(P0, d0, args.rays or n_batch)
+    batch = vrt.RayBatch(rays[0], rays[1], "fp64")
+    wall, per = time_traces(vrt, torch, med, batch, prm, "fp64", max(1, args.steps), 1)
+    cnt = vrt.counters(ctx, batch)
+    ms = float(np.mean(per))
+    value = cnt["steps"] / (ms / 1e3)
+    print(f"[helix] batch of {batch.n}: {ms:.1f} ms per trace, {value:.4g} ray-steps/s",
+          file=sys.stderr, flush=True)
+    # the paper's single ray with its polyline
+    b1 = vrt.RayBatch(P0, d0, "fp64")
+    cap = 808_400
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    path, npts = vrt.trace_paths(med, b1, prm, cap)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    one_ms = e0.elapsed_time(e1)
+    res = b1.results()
+    m = int(npts[0])
+    pts = path[:min(m, cap), 0].cpu().numpy()
+    ins = pts[pts[:, 2] >= 0.0]
+    z = ins[:, 2]
+    rho0, kap = hx["rho0"], hx["kappa"]
+    rmse = math.sqrt(np.mean((ins[:, 0] - rho0 * np.cos(kap * z)) ** 2 +
+                             (ins[:, 1] - rho0 * np.sin(kap * z)) ** 2))
+    achieved = HELIX_FLOPS_PER_STEP * value / 1e12
+    out = {"metric": METRIC, "value": value, "unit": "ray-steps/s", "n_gpus": 1,
+           "steps": len(per), "warmup": 1, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "helical ray of Sec. IV: parabolic fiber n_c = 1.38, "
+                                  "Delta = 0.2, R = 5, length 55, dL0 = 1e-4; "
+                                  f"{batch.n} copies turned about the axis, plain FP64 march",
+                      "rays": batch.n, "ray_steps_per_trace": cnt["steps"]},
+           "single_ray": {"ms": round(one_ms, 3), "ray_steps_per_s": int(res["steps"][0]) / (one_ms / 1e3),
+                          "points": m, "points_inside": int(len(ins)), "rmse": rmse,
+                          "kernel": "record_paths_kernel",
+                          "paper": {"points": 808360, "rmse": 5.0892e-5, "wall_s": 0.5157,
+                                    "hardware": "MATLAB R2024b, Apple M4 (trajectory + rendering)"}},
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                        "traffic": None, "algo_flops_per_ray_step": HELIX_FLOPS_PER_STEP,
+                        "kernel": "march_fp64_kernel"},
+           "counters": cnt}
+    if not args.no_cpu_baseline:
+        import oracle  # CPU-baseline leg only
+
+        oracle.build(force=False)
+        t0 = time.perf_counter()
+        op, ores = oracle.trace_path(spec, P0[0], d0[0], prm, cap=cap)
+        sec = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": ores["steps"] / sec, "unit": "ray-steps/s", "cores": 1,
+                               "kind": "oracle", "seconds": round(sec, 3),
+                               "sample": "the paper's single ray with its polyline recorded, FP64 "
+                                         "C oracle, one thread (one ray)"}
+        k = min(len(op), len(pts))
+        out["parity_vs_oracle"] = {"points_equal_count": bool(ores["n_path"] == m),
+                                   "max_point_diff": float(np.abs(pts[:k] - op[:k]).max()),
+                                   "batch_steps_equal": bool(np.all(batch.results()["steps"] ==
+                                                                    ores["steps"]))}
+    med.close()
+    ctx.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="freeform",
-                    choices=["freeform", "grid", "luneburg", "zernike", "spherical", "served",
-                             "n2p", "adjoint"])
+                    choices=["freeform", "grid", "luneburg", "zernike", "spherical", "helix",
+                             "served", "n2p", "adjoint"])
     ap.add_argument("--jobs", type=int, default=120, help="served: jobs in the arrival stream")
     ap.add_argument("--load", type=float, default=0.8,
                     help="served: offered load as a fraction of the measured capacity")
@@ -553,6 +645,9 @@ def main(argv=None):
         return 0
     if args.workload == "adjoint":
         print(json.dumps(adjoint_bench(vrt, torch, args)), flush=True)
+        return 0
+    if args.workload == "helix":
+        print(json.dumps(helix_bench(vrt, torch, args)), flush=True)
         return 0
     spec, rays, prm, precision, desc, aperture = build_workload(args.workload, args.rays)
     n_rays = rays[0].shape[0]

@@ -212,6 +212,26 @@ int vrt_medium_device_bytes(vrt_medium_t m, size_t *out);
 int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, size_t n_rays,
               void *stream);
 
+/* Trace n_rays rays with the plain double-precision march (p->precision must
+ * be VRT_FP64) and record each ray's polyline P_0, P_1, ... of Sec. II
+ * (Eqs. (3)-(4)): the launch point, the entry point on the enclosing surface,
+ * the end of every constant-OPL step, and every point where a step meets the
+ * surface (boundary TIR, exit).  The exit-plane continuation is not part of
+ * the polyline.  Asynchronous on `stream`; the exit states go to `rays` as in
+ * vrt_trace.
+ *   path      device array of n_rays * cap * 3 doubles, point-major: point k
+ *             of ray r at path[(k * n_rays + r) * 3 + {0,1,2}] for
+ *             k < min(cap, n_points[r]); other entries are left untouched.
+ *   cap       points kept per ray, >= 1.
+ *   n_points  device array of n_rays uint64: the number of points of each
+ *             ray's polyline (it may exceed cap; then only the first cap are
+ *             stored).
+ * The caller owns path and n_points.  Errors: as vrt_trace, and EINVAL for
+ * another precision, cap == 0 or n_rays * cap * 24 bytes beyond the address
+ * space, and a null or misaligned path or n_points. */
+int vrt_trace_paths(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays,
+                    size_t n_rays, double *path, uint64_t cap, uint64_t *n_points, void *stream);
+
 /* Sum the per-ray outputs of a finished trace (status, steps, n_tir, n_btir,
  * flags of `rays`) into *out.  Runs a reduction kernel on `stream` and
  * synchronises that stream.  Errors: EINVAL, EHIP. */

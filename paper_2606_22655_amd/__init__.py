@@ -34,7 +34,8 @@ EXPORTED = ["vrt_abi_version", "vrt_context_create", "vrt_context_destroy",
             "vrt_medium_create_analytic", "vrt_medium_create_grid", "vrt_medium_destroy",
             "vrt_medium_device_bytes", "vrt_trace", "vrt_reduce_counters", "vrt_last_error",
             "vrt_server_create", "vrt_server_submit", "vrt_server_query", "vrt_server_wait",
-            "vrt_server_stats_get", "vrt_server_destroy", "vrt_n2p_sweep", "vrt_grid_loss_grad"]
+            "vrt_server_stats_get", "vrt_server_destroy", "vrt_n2p_sweep", "vrt_grid_loss_grad",
+            "vrt_trace_paths"]
 JOB_STATES = {0: "QUEUED", 1: "RUNNING", 2: "COPYING", 3: "DONE"}
 
 
@@ -117,6 +118,8 @@ def load_library(path=LIB_PATH):
     lib.vrt_medium_destroy.argtypes = [vp]
     lib.vrt_medium_device_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
     lib.vrt_trace.argtypes = [vp, C.POINTER(vrt_trace_params), C.POINTER(vrt_rays), C.c_size_t, vp]
+    lib.vrt_trace_paths.argtypes = [vp, C.POINTER(vrt_trace_params), C.POINTER(vrt_rays),
+                                    C.c_size_t, vp, C.c_uint64, vp, vp]
     lib.vrt_reduce_counters.argtypes = [vp, C.POINTER(vrt_rays), C.c_size_t,
                                         C.POINTER(vrt_counters), vp]
     lib.vrt_server_create.argtypes = [vp, C.c_size_t, i32, C.POINTER(vp)]
@@ -200,6 +203,12 @@ def vrt_medium_device_bytes(m):
 def vrt_trace(medium, params, rays, n_rays, stream):
     return _check(load_library().vrt_trace(medium, C.byref(params), C.byref(rays), int(n_rays),
                                            C.c_void_p(stream)))
+
+
+def vrt_trace_paths(medium, params, rays, n_rays, path, cap, n_points, stream):
+    return _check(load_library().vrt_trace_paths(medium, C.byref(params), C.byref(rays),
+                                                 int(n_rays), C.c_void_p(path), int(cap),
+                                                 C.c_void_p(n_points), C.c_void_p(stream)))
 
 
 def vrt_n2p_sweep(lens, beta_gamma, y, z_launch, params, stream=0, want_z=False,
@@ -477,6 +486,22 @@ def trace(medium, batch, params, precision, stream=None):
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     vrt_trace(medium.handle, make_params(params, precision), batch.rays, batch.n, stream)
+
+
+def trace_paths(medium, batch, params, cap, stream=None):
+    """Enqueue the FP64 march of ``batch`` (an fp64 RayBatch) with its
+    polylines recorded; returns device tensors ``path`` (cap, n, 3), point k
+    of ray r at path[k, r], and ``n_points`` (n,) int64 (points of each
+    polyline, possibly above cap)."""
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    path = torch.empty((int(cap), batch.n, 3), dtype=torch.float64, device=batch.inp.device)
+    n_points = torch.empty((batch.n,), dtype=torch.int64, device=batch.inp.device)
+    vrt_trace_paths(medium.handle, make_params(params, "fp64"), batch.rays, batch.n,
+                    path.data_ptr() if batch.n else None, cap,
+                    n_points.data_ptr() if batch.n else None, stream)
+    return path, n_points
 
 
 def counters(ctx, batch, stream=None):

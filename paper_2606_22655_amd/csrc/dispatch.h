@@ -22,5 +22,7 @@ struct LaunchArgs {
 
 hipError_t launch_march_fp64(const LaunchArgs &a);
 hipError_t launch_march_fp32c(const LaunchArgs &a);
+hipError_t launch_paths_fp64(const LaunchArgs &a, double *path, uint64_t cap,
+                             uint64_t *n_points);
 
 }  // namespace vrt

@@ -14,9 +14,31 @@ struct Out64 {
     uint32_t status, steps, ntir, nbtir, flags;
 };
 
-template <int MK>
+// Polyline recorders: NoPath records nothing (the batch kernels); PathRec
+// stores the points of the polyline -- the launch point, the entry point,
+// every step's end and every point where a step meets the surface -- at
+// buf + k * stride for point k < cap, and counts them all.
+struct NoPath {
+    __device__ __forceinline__ void add(const d3 &) {}
+};
+struct PathRec {
+    double *buf;
+    uint64_t cap, n;
+    size_t stride;
+    __device__ __forceinline__ void add(const d3 &P) {
+        if (n < cap) {
+            double *q = buf + n * stride;
+            q[0] = P.x;
+            q[1] = P.y;
+            q[2] = P.z;
+        }
+        ++n;
+    }
+};
+
+template <int MK, class Path>
 __device__ void trace_ray64(const MediumDev &m, const BoundaryDev &b, const TraceDev &t, d3 P0,
-                            d3 d0, Out64 &o) {
+                            d3 d0, Out64 &o, Path &path) {
     o.P = P0;
     o.D = d0;
     o.status = VRT_RAY_EXITED;
@@ -28,6 +50,7 @@ __device__ void trace_ray64(const MediumDev &m, const BoundaryDev &b, const Trac
     }
     d3 I = mk(d0.x / l0, d0.y / l0, d0.z / l0);  // unit launch direction
     d3 P = P0, R = I;
+    path.add(P);
     double n_last, Delta = 0.0;  // n_last = n at the previous polyline point
     bool decide;
     if (surf_inside_strict(b, P)) {
@@ -43,6 +66,7 @@ __device__ void trace_ray64(const MediumDev &m, const BoundaryDev &b, const Trac
         }
         P = P + tt * I;  // straight in the surroundings (case (iii))
         surf_snap(b, P, face);
+        path.add(P);
         d3 N = surf_normal(b, P, face);
         double n_in = index64<MK>(m, P);
         double mu = m.n_amb / n_in, c = dot(N, I);
@@ -110,6 +134,7 @@ __device__ void trace_ray64(const MediumDev &m, const BoundaryDev &b, const Trac
             if (tx > Delta) {
                 P = P + Delta * R;
                 I = R;
+                path.add(P);
                 if ((int64_t)o.steps >= t.max_steps) {
                     o.status = VRT_RAY_TRUNCATED;
                     o.P = P;
@@ -120,6 +145,7 @@ __device__ void trace_ray64(const MediumDev &m, const BoundaryDev &b, const Trac
             }
             P = P + tx * R;
             surf_snap(b, P, face);
+            path.add(P);
             d3 N = surf_normal(b, P, face);
             double mu = n_last / m.n_amb, c = dot(N, R);
             double D = 1.0 - mu * mu * (1.0 - c * c);
@@ -153,6 +179,13 @@ __device__ void trace_ray64(const MediumDev &m, const BoundaryDev &b, const Trac
             return;
         }
     }
+}
+
+template <int MK>
+__device__ __forceinline__ void trace_ray64(const MediumDev &m, const BoundaryDev &b,
+                                            const TraceDev &t, d3 P0, d3 d0, Out64 &o) {
+    NoPath none;
+    trace_ray64<MK>(m, b, t, P0, d0, o, none);
 }
 
 }  // namespace vrt

@@ -483,38 +483,40 @@ int vrt_medium_device_bytes(vrt_medium_t m, size_t *out) {
 
 static bool aligned(const void *p, size_t a) { return p && ((uintptr_t)p % a) == 0; }
 
-int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, size_t n_rays,
-              void *stream) {
-    if (!m || !p || !rays) return fail(VRT_EINVAL, "vrt_trace: NULL argument");
-    if (!(p->dL0 > 0.0) || !isfinite(p->dL0)) return fail(VRT_EINVAL, "vrt_trace: dL0 must be > 0");
+// Argument checks shared by vrt_trace and vrt_trace_paths.
+static int check_trace_args(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays,
+                            size_t n_rays, const char *who) {
+    if (!m || !p || !rays) return fail(VRT_EINVAL, "%s: NULL argument", who);
+    if (!(p->dL0 > 0.0) || !isfinite(p->dL0)) return fail(VRT_EINVAL, "%s: dL0 must be > 0", who);
     if (p->max_steps <= 0 || p->max_steps > 0xFFFFFFFFll)
-        return fail(VRT_EINVAL, "vrt_trace: max_steps must be in [1, 2^32)");
+        return fail(VRT_EINVAL, "%s: max_steps must be in [1, 2^32)", who);
     if (p->max_lanes < 0 || (p->precision == VRT_FP64 && p->max_lanes != 0))
-        return fail(VRT_EINVAL, "vrt_trace: max_lanes must be >= 0 (and 0 for VRT_FP64)");
+        return fail(VRT_EINVAL, "%s: max_lanes must be >= 0 (and 0 for VRT_FP64)", who);
     if (!(p->eps_tan >= 0.0) || !(p->crit_rad >= 0.0) || !(p->tie_eps >= 0.0) ||
         !(p->tie_eps <= 1e-6))
-        return fail(VRT_EINVAL, "vrt_trace: eps_tan, crit_rad >= 0 and tie_eps in [0, 1e-6]");
+        return fail(VRT_EINVAL, "%s: eps_tan, crit_rad >= 0 and tie_eps in [0, 1e-6]", who);
     if (p->precision != VRT_FP64 && p->precision != VRT_FP32_COMP)
-        return fail(VRT_EINVAL, "vrt_trace: unknown precision %d", p->precision);
-    if (n_rays >= (1ull << 31)) return fail(VRT_EINVAL, "vrt_trace: n_rays must be < 2^31");
+        return fail(VRT_EINVAL, "%s: unknown precision %d", who, p->precision);
+    if (n_rays >= (1ull << 31)) return fail(VRT_EINVAL, "%s: n_rays must be < 2^31", who);
     if (p->precision == VRT_FP32_COMP && p->dL0 > m->fp32_max_dL0)
         return fail(VRT_EINVAL,
-                    "vrt_trace: dL0 = %g exceeds %g, the longest step the single-precision path "
+                    "%s: dL0 = %g exceeds %g, the longest step the single-precision path "
                     "keeps accurate in this medium (0.05 n_min sigma_min); use VRT_FP64",
-                    p->dL0, m->fp32_max_dL0);
+                    who, p->dL0, m->fp32_max_dL0);
     if (n_rays == 0) return VRT_OK;
     const size_t es = p->precision == VRT_FP64 ? 8 : 4;
     const void *ptrs[] = {rays->px, rays->py, rays->pz, rays->dx, rays->dy, rays->dz,
                           rays->ox, rays->oy, rays->oz, rays->odx, rays->ody, rays->odz};
     for (const void *q : ptrs)
-        if (!aligned(q, es)) return fail(VRT_EINVAL, "vrt_trace: ray array NULL or misaligned");
+        if (!aligned(q, es)) return fail(VRT_EINVAL, "%s: ray array NULL or misaligned", who);
     const void *uptrs[] = {rays->status, rays->steps, rays->n_tir, rays->n_btir, rays->flags};
     for (const void *q : uptrs)
-        if (!aligned(q, 4)) return fail(VRT_EINVAL, "vrt_trace: result array NULL or misaligned");
-    vrt_context_t ctx = m->ctx;
-    int rc = set_device(ctx);
-    if (rc) return rc;
-    LaunchArgs a{};
+        if (!aligned(q, 4)) return fail(VRT_EINVAL, "%s: result array NULL or misaligned", who);
+    return VRT_OK;
+}
+
+static void fill_launch(vrt_medium_t m, const vrt_trace_params *p, size_t n_rays, void *stream,
+                        LaunchArgs &a) {
     a.m = m->dev;
     a.mf = m->mf;
     a.b = m->bnd;
@@ -527,17 +529,32 @@ int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, s
     a.t.plane_z = a.t.has_plane ? p->exit_plane_z : 0.0;
     a.n = (uint32_t)n_rays;
     a.stream = (hipStream_t)stream;
-    a.num_cu = ctx->num_cu;
+    a.num_cu = m->ctx->num_cu;
     a.blocks_per_cu = 0;
     a.max_blocks = p->max_lanes > 0 ? (uint32_t)((p->max_lanes + 255) / 256) : 0u;
+}
+
+static RaysDev<double> rays64(const vrt_rays *rays) {
+    return RaysDev<double>{(const double *)rays->px, (const double *)rays->py,
+                           (const double *)rays->pz, (const double *)rays->dx,
+                           (const double *)rays->dy, (const double *)rays->dz,
+                           (double *)rays->ox, (double *)rays->oy, (double *)rays->oz,
+                           (double *)rays->odx, (double *)rays->ody, (double *)rays->odz,
+                           rays->status, rays->steps, rays->n_tir, rays->n_btir, rays->flags};
+}
+
+int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, size_t n_rays,
+              void *stream) {
+    if (int rc = check_trace_args(m, p, rays, n_rays, "vrt_trace")) return rc;
+    if (n_rays == 0) return VRT_OK;
+    vrt_context_t ctx = m->ctx;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    LaunchArgs a{};
+    fill_launch(m, p, n_rays, stream, a);
     hipError_t e;
     if (p->precision == VRT_FP64) {
-        a.io64 = RaysDev<double>{(const double *)rays->px, (const double *)rays->py,
-                                 (const double *)rays->pz, (const double *)rays->dx,
-                                 (const double *)rays->dy, (const double *)rays->dz,
-                                 (double *)rays->ox, (double *)rays->oy, (double *)rays->oz,
-                                 (double *)rays->odx, (double *)rays->ody, (double *)rays->odz,
-                                 rays->status, rays->steps, rays->n_tir, rays->n_btir, rays->flags};
+        a.io64 = rays64(rays);
         e = launch_march_fp64(a);
     } else {
         a.io32 = RaysDev<float>{(const float *)rays->px, (const float *)rays->py,
@@ -551,6 +568,27 @@ int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, s
         e = launch_march_fp32c(a);
     }
     if (e != hipSuccess) return fail_hip(e, "vrt_trace: launch");
+    return VRT_OK;
+}
+
+int vrt_trace_paths(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays,
+                    size_t n_rays, double *path, uint64_t cap, uint64_t *n_points, void *stream) {
+    if (int rc = check_trace_args(m, p, rays, n_rays, "vrt_trace_paths")) return rc;
+    if (p->precision != VRT_FP64)
+        return fail(VRT_EINVAL, "vrt_trace_paths: paths are recorded by the VRT_FP64 march");
+    if (cap == 0 || cap > (1ull << 40) || (n_rays > 0 && cap > SIZE_MAX / 24 / n_rays))
+        return fail(VRT_EINVAL, "vrt_trace_paths: cap must be in [1, 2^40] with n_rays * cap * 24 "
+                                "bytes addressable");
+    if (n_rays == 0) return VRT_OK;
+    if (!aligned(path, 8) || !aligned(n_points, 8))
+        return fail(VRT_EINVAL, "vrt_trace_paths: path or n_points NULL or misaligned");
+    int rc = set_device(m->ctx);
+    if (rc) return rc;
+    LaunchArgs a{};
+    fill_launch(m, p, n_rays, stream, a);
+    a.io64 = rays64(rays);
+    hipError_t e = launch_paths_fp64(a, path, cap, n_points);
+    if (e != hipSuccess) return fail_hip(e, "vrt_trace_paths: launch");
     return VRT_OK;
 }
 

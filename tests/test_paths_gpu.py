@@ -1,0 +1,156 @@
+"""GPU: recorded polylines (vrt_trace_paths) -- the points P_0, P_1, ... of
+Sec. II (Eqs. (3)-(4)) from the plain FP64 march, point by point against the
+oracle's recorded path, and the paper's helix benchmark (Sec. IV) rerun on
+the GPU: 808,360 points and the transverse RMSE against the analytic helix."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from test_oracle_pins import helix_setup
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vrt():
+    import torch
+
+    import paper_2606_22655_amd as vrt
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    vrt.load_library()
+    return vrt
+
+
+@pytest.fixture(scope="module")
+def ctx(vrt):
+    c = vrt.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_paths(vrt, ctx, spec, rays, prm, cap):
+    import torch
+
+    med = vrt.Medium(ctx, spec)
+    try:
+        b = vrt.RayBatch(rays[0], rays[1], "fp64")
+        path, npts = vrt.trace_paths(med, b, prm, cap)
+        torch.cuda.synchronize()
+        return path.cpu().numpy(), npts.cpu().numpy(), b.results()
+    finally:
+        med.close()
+
+
+def helix_rmse(path, kappa, rho0):
+    ins = path[path[:, 2] >= 0.0]
+    z = ins[:, 2]
+    return len(ins), math.sqrt(np.mean((ins[:, 0] - rho0 * np.cos(kappa * z)) ** 2 +
+                                       (ins[:, 1] - rho0 * np.sin(kappa * z)) ** 2))
+
+
+def test_helix_path_reproduces_the_paper_on_the_gpu(vrt, ctx, orc):
+    """E1: one ray, dL0 = 1e-4, 808,360 points inside the fiber; the GPU's
+    points equal the oracle's to rounding, and the RMSE against the analytic
+    helix is the paper's 5.0892e-5 to 10 % (the oracle's own pin)."""
+    gold, med, P0, d0, kappa, rho0 = helix_setup()
+    prm = {"dL0": gold["dL0"], "max_steps": 2_000_000}
+    opath, ores = orc.trace_path(med, P0, d0, prm)
+    path, npts, res = gpu_paths(vrt, ctx, med, (P0[None], d0[None]), prm, cap=len(opath) + 8)
+    assert res["status"][0] == ores["status"] == orc.EXITED
+    assert int(npts[0]) == len(opath) == ores["n_path"]
+    g = path[:npts[0], 0]
+    err = np.abs(g - opath).max()
+    print(f"\n[paths] helix: {npts[0]} points, max |GPU - oracle| = {err:.3e}", flush=True)
+    assert err < 1e-9
+    m, rmse = helix_rmse(g, kappa, rho0)
+    m_o, rmse_o = helix_rmse(opath, kappa, rho0)
+    print(f"[paths] helix RMSE GPU {rmse:.6e}, oracle {rmse_o:.6e}, paper {gold['rmse']:.6e} "
+          f"({m} points inside, paper {gold['m_points']})", flush=True)
+    assert m == m_o and abs(m - gold["m_points"]) <= 1
+    assert abs(rmse - rmse_o) < 1e-6 * rmse_o
+    assert abs(rmse / gold["rmse"] - 1.0) < 0.10
+
+
+def media_cases():
+    lun, (P0, d0), _ = workloads.luneburg_beam(n_side=6)
+    yield "luneburg", lun, (P0, d0), workloads.trace_params(2e-3, 20000), 400
+    spec, rays, _ = workloads.gaussian_cube(n_rays=100)
+    yield "gaussian", spec, rays, workloads.trace_params(2e-3, 20000), 5000
+    yield "zernike", workloads.zernike_lens(), workloads.zernike_rays(40, seed=35), \
+        workloads.trace_params(5e-3, 20000), 3000
+    yield "n2p", workloads.n2p_lens(0.6791, 5.0069, 0.3), workloads.n2p_rays(0.3), \
+        workloads.trace_params(1e-3, 20000), 1000
+    grid = workloads.grid_medium(workloads.noise_grid(24, 505))
+    yield "grid", grid, workloads.face_cone_rays(70, 36, 25.0), workloads.trace_params(2e-3, 300), 200
+
+
+@pytest.mark.parametrize("case", [c[0] for c in media_cases()])
+def test_paths_match_the_oracle(vrt, ctx, orc, case):
+    """Every recorded point, the point counts (also beyond cap: the Luneburg
+    and grid cases keep fewer points than their paths hold) and the exit
+    states equal those of vrt_trace."""
+    name, spec, rays, prm, cap = next(c for c in media_cases() if c[0] == case)
+    P0, d0 = rays
+    path, npts, res = gpu_paths(vrt, ctx, spec, rays, prm, cap)
+    n = P0.shape[0]
+    clipped = 0
+    for r in range(n):
+        op, ores = orc.trace_path(spec, P0[r], d0[r], prm)
+        assert int(npts[r]) == ores["n_path"], (case, r)
+        k = min(cap, int(npts[r]))
+        clipped += int(npts[r]) > cap
+        # the two FP64 marches differ only in the rounding of the index (polar
+        # against Cartesian forms, operation order): 1e-8 leaves room for its
+        # growth along the longest paths
+        assert np.abs(path[:k, r] - op[:k]).max() < 1e-8, (case, r)
+    import torch
+
+    med = vrt.Medium(ctx, spec)
+    try:
+        b = vrt.RayBatch(P0, d0, "fp64")
+        vrt.trace(med, b, prm, "fp64")
+        torch.cuda.synchronize()
+        plain = b.results()
+    finally:
+        med.close()
+    for k in ("P", "D", "status", "steps", "ntir", "nbtir", "flags"):
+        assert np.array_equal(plain[k], res[k]), (case, k)
+    print(f"\n[paths] {case}: {n} rays, {clipped} beyond cap {cap}", flush=True)
+    if case in ("luneburg", "grid"):
+        assert clipped > 0
+
+
+def test_paths_refusals_and_empty_batch(vrt, ctx):
+    import torch
+
+    med = vrt.Medium(ctx, workloads.luneburg_beam(n_side=2)[0])
+    try:
+        P0, d0 = np.array([[0.1, 0.2, -1.5]]), np.array([[0.0, 0.0, 1.0]])
+        b = vrt.RayBatch(P0, d0, "fp64")
+        prm = vrt.make_params({"dL0": 1e-3, "max_steps": 10000}, "fp64")
+        path = torch.empty((10, 1, 3), dtype=torch.float64, device="cuda")
+        npts = torch.empty((1,), dtype=torch.int64, device="cuda")
+        stream = torch.cuda.current_stream().cuda_stream
+        with pytest.raises(vrt.VrtError):  # single precision does not record
+            vrt.vrt_trace_paths(med.handle, vrt.make_params({"dL0": 1e-3, "max_steps": 10000},
+                                                            "fp32c"),
+                                b.rays, 1, path.data_ptr(), 10, npts.data_ptr(), stream)
+        with pytest.raises(vrt.VrtError):  # cap 0
+            vrt.vrt_trace_paths(med.handle, prm, b.rays, 1, path.data_ptr(), 0, npts.data_ptr(),
+                                stream)
+        with pytest.raises(vrt.VrtError):  # no path buffer
+            vrt.vrt_trace_paths(med.handle, prm, b.rays, 1, None, 10, npts.data_ptr(), stream)
+        with pytest.raises(vrt.VrtError):  # misaligned counts
+            vrt.vrt_trace_paths(med.handle, prm, b.rays, 1, path.data_ptr(), 10,
+                                npts.data_ptr() + 4, stream)
+        empty = vrt.RayBatch(np.zeros((0, 3)), np.zeros((0, 3)), "fp64")
+        p0, n0 = vrt.trace_paths(med, empty, {"dL0": 1e-3, "max_steps": 10}, 4)
+        assert p0.shape == (4, 0, 3) and n0.shape == (0,)
+        p1, n1 = vrt.trace_paths(med, b, {"dL0": 1e-3, "max_steps": 10000}, 10)
+        torch.cuda.synchronize()
+        assert int(n1[0]) > 10 and np.allclose(p1[0, 0].cpu().numpy(), P0[0])
+    finally:
+        med.close()

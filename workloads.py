@@ -91,6 +91,28 @@ def luneburg_beam(n_side=64, R=1.0, z0=-1.5, dL0=1e-3, max_steps=20000):
     return medium, (P0, d0), trace_params(dL0, max_steps)
 
 
+def helix_fiber(n_c=1.38, Delta=0.2, R=5.0, rho0=4.0, L=55.0):
+    """The helical ray of Sec. IV (Eq. (21), Fig. 2): a parabolic-index fiber
+    of core index n_c and radius R along z in 0 <= z <= L, surrounded by the
+    cladding index n_c sqrt(1 - 2 Delta) (also before the fiber face), and one
+    ray launched so that it enters at P_I = (rho0, 0, 0) and winds on the
+    cylinder of radius rho0.  With n^2 = n_c^2 - w^2 rho^2, w = n_c sqrt(2
+    Delta) / R, a helix of radius rho0 needs tangential momentum w rho0 (seen
+    in the cladding) and axial invariant b = sqrt(n_c^2 - 2 w^2 rho0^2); its
+    closed form is (rho0 cos kz, rho0 sin kz, z) with k = w / b.  Returns
+    (medium, (P0, d0) of shape (1, 3), {"rho0", "kappa"}).  No random draws."""
+    ncl = n_c * math.sqrt(1.0 - 2.0 * Delta)
+    w = n_c * math.sqrt(2.0 * Delta) / R
+    b = math.sqrt(n_c ** 2 - 2.0 * w ** 2 * rho0 ** 2)
+    s = w * rho0 / ncl
+    d0 = np.array([[0.0, s, math.sqrt(1.0 - s * s)]])
+    P0 = np.array([[rho0, 0.0, 0.0]]) - rho0 * d0
+    medium = {"kind": "fiber", "params": np.array([n_c, Delta, R, 0.0, 0.0]),
+              "boundary": {"kind": "cylinder", "params": np.array([0.0, 0.0, R, 0.0, L])},
+              "n_amb": ncl}
+    return medium, (P0, d0), {"rho0": rho0, "kappa": w / b}
+
+
 # ---------------------------------------------------------------------------
 # Launch states on the z = 0 face of the unit cube
 # ---------------------------------------------------------------------------
