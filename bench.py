@@ -163,6 +163,17 @@ def time_traces(vrt, torch, med, batch, prm, precision, steps, warmup):
     return wall, per
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(spec, rays, prm, sample, g_res, aperture):
     import oracle  # CPU-baseline leg only
 
@@ -174,7 +185,12 @@ def cpu_baseline(spec, rays, prm, sample, g_res, aperture):
     base = {"value": steps / r["seconds"], "unit": "ray-steps/s", "cores": threads,
             "kind": "oracle", "seconds": round(r["seconds"], 3),
             "sample": f"first {n} rays of the same workload ({steps} ray-steps), FP64 C oracle, "
-                      f"OpenMP {threads} threads"}
+                      f"OpenMP {threads} threads", "cpu_model": cpu_model()}
+    # the same oracle on one core, on the first 1/32 of the sample
+    n1 = max(1, n // 32)
+    r1 = oracle.trace(spec, (rays[0][:n1], rays[1][:n1]), prm, n_threads=1)
+    base["one_core"] = {"value": int(r1["steps"].sum()) / r1["seconds"], "rays": n1,
+                        "seconds": round(r1["seconds"], 3)}
     sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
     from parity import compare
 
