@@ -50,8 +50,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("march_fp32c.hip", "lane32.h", "media.h", "vrt_common.h", "dispatch.h")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {  # workload -> (fetch KiB, write KiB, kernel sha256); profiles/march_fp32c_hbm_traffic.md
-    "freeform": (79688.0, 322763.0, "6dfbc59bcdac518e9db2be7fe5d23c5385ec72ca965c90e787567882bfff6e12"),
-    "grid": (409719685.8, 1584176.6, "6dfbc59bcdac518e9db2be7fe5d23c5385ec72ca965c90e787567882bfff6e12"),
+    "freeform": (79912.7, 322475.0, "d88ce48fcbf6f13c5088aa9da37e82ee3ef631fb23a3ba6665529cc105a425f2"),
+    "grid": (409723745.8, 1584066.7, "d88ce48fcbf6f13c5088aa9da37e82ee3ef631fb23a3ba6665529cc105a425f2"),
 }
 
 

@@ -72,6 +72,10 @@ __global__ __launch_bounds__(256) void adj_forward_kernel(MediumDev m, BoundaryD
     fwd_entry(m, b, t, mk(in.px[r], in.py[r], in.pz[r]), mk(in.dx[r], in.dy[r], in.dz[r]), s, end);
     uint32_t o = 0;
     double x = 0.0, y = 0.0;
+    // Ops alternate decide, move (a boundary TIR adds a move).  One iteration
+    // runs one op and then the move that follows a decide, so lanes of a wave
+    // that fell out of step after a boundary TIR are back in step at the next
+    // iteration instead of running decides and moves on alternate passes.
     while (s.phase != PH_DONE) {
         if (ck && o % kops == 0) {
             if (o / kops >= n_ck) {  // cannot happen within max_steps; never write past the buffer
@@ -80,8 +84,20 @@ __global__ __launch_bounds__(256) void adj_forward_kernel(MediumDev m, BoundaryD
             }
             put_state(ck, o / kops, lane, n, s);
         }
+        const bool decided = s.phase == PH_DECIDE;
         fwd_op(m, b, t, s, x, y, end);
         ++o;
+        if (decided && s.phase == PH_MOVE) {
+            if (ck && o % kops == 0) {
+                if (o / kops >= n_ck) {
+                    end = END_OTHER;
+                    break;
+                }
+                put_state(ck, o / kops, lane, n, s);
+            }
+            fwd_op(m, b, t, s, x, y, end);
+            ++o;
+        }
     }
     if (end != END_PLANE) end = END_OTHER;
     double l = 0.0;
@@ -122,13 +138,29 @@ __global__ __launch_bounds__(256, 2) void adj_backward_kernel(MediumDev m, Bound
         const uint32_t o1 = min(total, o0 + kops);
         double x, y;
         int end;
-        for (uint32_t o = o0; o < o1; ++o) {
+        for (uint32_t o = o0; o < o1;) {  // the forward kernel's op pairing
+            const bool decided = s.phase == PH_DECIDE;
             put_state(tape, o - o0, lane, n, s);
             fwd_op(m, b, t, s, x, y, end);
+            ++o;
+            if (decided && o < o1 && s.phase == PH_MOVE) {
+                put_state(tape, o - o0, lane, n, s);
+                fwd_op(m, b, t, s, x, y, end);
+                ++o;
+            }
         }
-        for (uint32_t o = o1; o-- > o0;) {
+        for (uint32_t o = o1; o > o0;) {  // reversed, the same (decide, move) pairs
+            --o;
             const St si = get_state(tape, o - o0, lane, n);
+            const bool moved = si.phase == PH_MOVE;
             vjp_op(m, b, t, si, a, xbar, ybar, acc);
+            if (moved && o > o0) {
+                const St sp = get_state(tape, o - 1 - o0, lane, n);
+                if (sp.phase == PH_DECIDE) {
+                    --o;
+                    vjp_op(m, b, t, sp, a, xbar, ybar, acc);
+                }
+            }
         }
     }
     vjp_entry(m, b, t, mk(in.px[r], in.py[r], in.pz[r]), mk(in.dx[r], in.dy[r], in.dz[r]), a, acc);
