@@ -160,6 +160,41 @@ def test_grid_fp32c_statistics(vrt, ctx, grid_case):
     assert_stats(rep)
 
 
+def test_grid_full_size_sampled(vrt, ctx, orc):
+    """The 4M-ray quantized-grid configuration in the launch configuration
+    the benchmark times.  Properties of every exit state; a seeded sample of
+    2,048 rays against the oracle over their first 128 moves (per ray, the
+    unstable ones counted and set aside); the exit-state statistics of 4,096
+    sampled full paths against the oracle's."""
+    spec, (P0, d0), prm = workloads.quantized_grid_cube()
+    n = P0.shape[0]
+    g = run_gpu(vrt, ctx, spec, (P0, d0), prm, "fp32c")
+    ok = g["status"] == 0
+    assert ok.mean() > 0.99
+    assert np.allclose(np.linalg.norm(g["D"][ok], axis=1), 1.0, atol=1e-5)
+    onface = np.min(np.minimum(np.abs(g["P"][ok]), np.abs(g["P"][ok] - 1.0)), axis=1)
+    assert onface.max() < 1e-6
+    rng = np.random.default_rng(2025)
+    idx = np.sort(rng.choice(n, 2048, replace=False))
+    p128 = dict(prm)
+    p128["max_steps"] = 128
+    g128 = run_gpu(vrt, ctx, spec, (P0, d0), p128, "fp32c")
+    sub = {k: v[idx] for k, v in g128.items()}
+    rays = (P0[idx], d0[idx])
+    o = orc.trace(spec, rays, p128)
+    bad = ill_conditioned(orc.trace, spec, rays, p128)
+    rep = compare(exempt(o, bad), exempt(sub, bad), aperture=1.0, spec=spec)
+    rep["ill_conditioned"] = int(bad.sum())
+    report("grid fp32c full-size sample, first 128 moves", rep)
+    assert bad.sum() <= 0.01 * len(bad)
+    assert_parity(rep)
+    idx = np.sort(rng.choice(n, 4096, replace=False))
+    o = orc.trace(spec, (P0[idx], d0[idx]), prm)
+    st = stat_compare(o, {k: v[idx] for k, v in g.items()})
+    print("[stats] grid fp32c full-size sample, full paths: " + json.dumps(st), flush=True)
+    assert_stats(st)
+
+
 # ---------------------------------------------------------------------------
 # the paper's helix (one ray, 808k steps) and other media / surfaces
 # ---------------------------------------------------------------------------
