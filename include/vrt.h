@@ -51,7 +51,7 @@ enum vrt_error {
     VRT_EINVAL = -1,       /* bad argument: null/misaligned pointer, dL0 <= 0, n <= 0, NaN parameter */
     VRT_ENOMEM = -2,       /* device allocation failed */
     VRT_EHIP = -3,         /* HIP runtime error; the message carries hipGetErrorString */
-    VRT_EUNSUPPORTED = -4, /* valid request this build does not implement */
+    VRT_EUNSUPPORTED = -4, /* valid request this library version does not implement */
     VRT_ETIMEOUT = -5      /* vrt_server_wait: the job is not done yet */
 };
 
@@ -207,7 +207,7 @@ int vrt_medium_device_bytes(vrt_medium_t m, size_t *out);
  * max_steps <= 0, max_lanes < 0 (or != 0 with VRT_FP64), unknown precision,
  * n_rays >= 2^31, and for VRT_FP32_COMP in a Gaussian-sum medium a dL0 above
  * 0.05 n_min sigma_min (the single-precision index difference is kept to its
- * stated accuracy only below that); EUNSUPPORTED for combinations this build
+ * stated accuracy only below that); EUNSUPPORTED for combinations this library version
  * does not implement; EHIP for launch failures. */
 int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, size_t n_rays,
               void *stream);
