@@ -50,8 +50,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("march_fp32c.hip", "lane32.h", "media.h", "vrt_common.h", "dispatch.h")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {  # workload -> (fetch KiB, write KiB, kernel sha256); profiles/march_fp32c_hbm_traffic.md
-    "freeform": (79912.7, 322475.0, "d88ce48fcbf6f13c5088aa9da37e82ee3ef631fb23a3ba6665529cc105a425f2"),
-    "grid": (409723745.8, 1584066.7, "d88ce48fcbf6f13c5088aa9da37e82ee3ef631fb23a3ba6665529cc105a425f2"),
+    "freeform": (79637.5, 322894.6, "acc26d3f4ec8a9a0c709cd00e03b5c11b4a749918dd81065a957706c508ec9f7"),
+    "grid": (408285068.2, 1583796.0, "acc26d3f4ec8a9a0c709cd00e03b5c11b4a749918dd81065a957706c508ec9f7"),
 }
 
 

@@ -76,6 +76,17 @@ __global__ void grid_records_kernel(const float *__restrict__ v, float4 *__restr
         const float hz = (v[(size_t)kh * sz + (size_t)j * sy + i] -
                           v[(size_t)kl * sz + (size_t)j * sy + i]) / (float)(kh - kl);
         rec[idx] = make_float4(c, hx, hy, hz);
+        // flag differences that float does not hold exactly (neighbouring
+        // values more than a factor 2 apart): the double-precision march then
+        // forms them from the node values instead of reading the records
+        const double ex = (double)v[row + ih] - (double)v[row + il];
+        const double ey = (double)v[(size_t)k * sz + (size_t)jh * sy + i] -
+                          (double)v[(size_t)k * sz + (size_t)jl * sy + i];
+        const double ez = (double)v[(size_t)kh * sz + (size_t)j * sy + i] -
+                          (double)v[(size_t)kl * sz + (size_t)j * sy + i];
+        if ((double)hx * (double)(ih - il) != ex || (double)hy * (double)(jh - jl) != ey ||
+            (double)hz * (double)(kh - kl) != ez)
+            atomicOr(bad, 2u);
     }
 }
 
@@ -450,12 +461,13 @@ int vrt_medium_create_grid(vrt_context_t ctx, const float *values, int nx, int n
         free_medium(m);
         return fail_hip(e, "vrt_medium_create_grid: records");
     }
-    if (hbad) {
+    if (hbad & 1u) {
         free_medium(m);
         return fail(VRT_EINVAL, "grid values must be finite and > 0");
     }
     d.grid = (const float *)g;
     d.rec = (const float4 *)r;
+    d.rec_exact = (hbad & 2u) ? 0 : 1;
     ctx->n_media++;
     *out = m;
     return VRT_OK;

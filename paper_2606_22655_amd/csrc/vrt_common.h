@@ -56,6 +56,7 @@ struct MediumDev {
     // discretized medium
     const float *grid;      // nz*ny*nx node values, x fastest
     const float4 *rec;      // nz*ny*nx node records (n, h_x, h_y, h_z), see media.h
+    int rec_exact;          // every h_a is the exact node difference over its spacings
     int nx, ny, nz;
     double lo[3], hi[3], h[3], inv_h[3];
     float flo[3], fhi[3], finv_h[3];

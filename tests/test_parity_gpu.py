@@ -138,6 +138,21 @@ def test_grid_fp64_identical(vrt, ctx, grid_case):
     tight(o, g, tol=1e-12)
 
 
+def test_grid_fp64_rough_values_identical(vrt, ctx, orc):
+    """A grid whose neighbouring values differ by up to 4x: its node
+    differences are not all exact in float, so the double-precision march
+    forms them from the node values; still the oracle's arithmetic."""
+    rng = np.random.default_rng(77)
+    vals = rng.uniform(1.0, 4.0, (20, 20, 20)).astype(np.float32)
+    spec = workloads.grid_medium(vals)
+    rays = workloads.face_cone_rays(2048, 78, 30.0)
+    prm = workloads.trace_params(1e-3, 5000)
+    o = orc.trace(spec, rays, prm)
+    g = run_gpu(vrt, ctx, spec, rays, prm, "fp64")
+    report("rough grid fp64", compare(o, g, aperture=1.0, spec=spec))
+    tight(o, g, tol=1e-12)
+
+
 def test_grid_fp32c_truncated_march(vrt, ctx, orc, grid_case):
     spec, rays, prm, _ = grid_case
     p128 = dict(prm)
