@@ -146,10 +146,19 @@ __device__ inline d3 grid_vjp(const MediumDev &m, d3 P, double nbar, d3 gbar, Gr
                 const double wz = dz ? f[2] : 1.0 - f[2];
                 const double w = wx * wy * wz;
                 const int i = c[0] + dx, j = c[1] + dy, k = c[2] + dz;
-                const double v = grid_node64(m, i, j, k);
-                const double hx = grid_cdiff64(m, i, j, k, 0);
-                const double hy = grid_cdiff64(m, i, j, k, 1);
-                const double hz = grid_cdiff64(m, i, j, k, 2);
+                double v, hx, hy, hz;
+                if (m.rec_exact) {  // the same doubles from the exact node record (media.h)
+                    const float4 r = m.rec[((size_t)k * m.ny + j) * m.nx + i];
+                    v = (double)r.x;
+                    hx = (double)r.y / m.h[0];
+                    hy = (double)r.z / m.h[1];
+                    hz = (double)r.w / m.h[2];
+                } else {
+                    v = grid_node64(m, i, j, k);
+                    hx = grid_cdiff64(m, i, j, k, 0);
+                    hy = grid_cdiff64(m, i, j, k, 1);
+                    hz = grid_cdiff64(m, i, j, k, 2);
+                }
                 const double sv = nbar * v + gbar.x * hx + gbar.y * hy + gbar.z * hz;
                 fbar[0] += (dx ? 1.0 : -1.0) * wy * wz * sv;
                 fbar[1] += (dy ? 1.0 : -1.0) * wx * wz * sv;
