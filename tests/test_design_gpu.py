@@ -94,6 +94,31 @@ def test_spherical_freeform_medium(vrt, ctx, orc, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_spherical_centre_takes_a_straight_step(vrt, ctx, orc, precision):
+    """Rays born at the centre of the spherical medium, where G2's gradient
+    has no limit (case (ii)): the first step is straight on both sides and
+    flagged, and the rays then match the oracle."""
+    spec = workloads.spherical_medium()
+    rng = np.random.default_rng(36)
+    d0 = rng.standard_normal((64, 3))
+    d0 /= np.linalg.norm(d0, axis=1)[:, None]
+    d0 = d0.astype(np.float32).astype(np.float64)
+    rays = (np.zeros((64, 3)), d0)
+    prm = workloads.trace_params(1e-3, 20000)
+    o = orc.trace(spec, rays, prm)
+    g = run_gpu(vrt, ctx, spec, rays, prm, precision)
+    assert np.all(o["flags"] & vrt.FLAG_STRAIGHT) and np.all(g["flags"] & vrt.FLAG_STRAIGHT)
+    if precision == "fp64":
+        rep = compare(o, g, aperture=2.0, spec=spec)
+    else:
+        bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-7, tol=1e-5, turn=1e-7)
+        rep = compare(exempt(o, bad), exempt(g, bad), aperture=2.0, spec=spec)
+        rep["ill_conditioned"] = int(bad.sum())
+    report(f"spherical centre {precision}", rep)
+    assert_parity(rep)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_n2p_lens_medium(vrt, ctx, orc, precision):
     spec = workloads.n2p_lens(0.6791, 5.0069, 0.2)
     rays = lens_rays(1500, 0.2, seed=32)
