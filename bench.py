@@ -185,7 +185,8 @@ def cpu_baseline(spec, rays, prm, sample, g_res, aperture):
     base = {"value": steps / r["seconds"], "unit": "ray-steps/s", "cores": threads,
             "kind": "oracle", "seconds": round(r["seconds"], 3),
             "sample": f"first {n} rays of the same workload ({steps} ray-steps), FP64 C oracle, "
-                      f"OpenMP {threads} threads", "cpu_model": cpu_model()}
+                      f"OpenMP {threads} threads", "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count()}
     # the same oracle on one core, on the first 1/32 of the sample
     n1 = max(1, n // 32)
     r1 = oracle.trace(spec, (rays[0][:n1], rays[1][:n1]), prm, n_threads=1)
