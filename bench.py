@@ -139,8 +139,9 @@ def build_workload(name, n_rays=None):
                 "FP32 + compensated sums, index in FP64")
         return spec, rays, prm, "fp32c", desc, 2.0
     if name == "luneburg":
-        spec, rays, prm = workloads.luneburg_beam()
-        desc = "Luneburg sphere R=1, 64x64 parallel beam, dL0 = 1e-3, plain FP64"
+        side = int(round(math.sqrt(n_rays))) if n_rays else 64
+        spec, rays, prm = workloads.luneburg_beam(n_side=side)
+        desc = f"Luneburg sphere R=1, {side}x{side} parallel beam, dL0 = 1e-3, plain FP64"
         return spec, rays, prm, "fp64", desc, 2.0
     raise ValueError(name)
 
@@ -694,8 +695,9 @@ def main(argv=None):
 
     flops = algo_flops_per_step(args.workload) * ray_steps
     achieved = flops / (ms / 1e3) / 1e12
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+    peak = PEAK_FP32_TFLOPS if precision == "fp32c" else PEAK_FP64_TFLOPS
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": traffic_bytes(args.workload) if precision == "fp32c" else None,
             "algo_flops_per_ray_step": algo_flops_per_step(args.workload),
             "kernel": "march_fp32c_kernel" if precision == "fp32c" else "march_fp64_kernel"}
