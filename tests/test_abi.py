@@ -102,3 +102,16 @@ def test_product_path_does_not_reference_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "liboracle" not in text and "import oracle" not in text, f
                 assert "from oracle" not in text and "vrt_oracle" not in text, f
+
+
+def test_missing_library_fails_loudly():
+    """Without libvrt.so the binding raises; there is no CPU fallback."""
+    import subprocess
+    import sys
+
+    code = ("import paper_2606_22655_amd as v\n"
+            "try:\n    v.load_library('/nonexistent/libvrt.so')\n"
+            "except ImportError as e:\n    print('raised', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0 and "raised" in r.stdout and "not built" in r.stdout, r.stderr
