@@ -1,0 +1,127 @@
+"""GPU: seeded random media and surfaces against the oracle, both march
+precisions.  Each case draws a medium kind (Gaussian sum, linear, Luneburg,
+fiber, homogeneous), its parameters, an enclosing surface (box, sphere,
+z-cylinder) and rays launched from outside towards points inside, so that
+entry refraction, reflection at entry, interior Snell/TIR, boundary TIR and
+exit refraction all occur across the cases.  The bar is the one every march
+parity test uses; in single precision the rays whose oracle result moves by
+1e-5 under a 1e-7 shift of the launch point or turn of its direction are set
+aside (counted, at most 10 %)."""
+import math
+
+import numpy as np
+import pytest
+
+from parity import assert_parity, compare, exempt, ill_conditioned
+
+pytestmark = pytest.mark.gpu
+
+N_CASES = 12
+
+
+@pytest.fixture(scope="module")
+def vrt():
+    import torch
+
+    import paper_2606_22655_amd as vrt
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    vrt.load_library()
+    return vrt
+
+
+@pytest.fixture(scope="module")
+def ctx(vrt):
+    c = vrt.Context(0)
+    yield c
+    c.close()
+
+
+def surface(rng, kind):
+    """An enclosing surface around the origin-centred unit region."""
+    if kind == "box":
+        lo = -rng.uniform(0.6, 1.0, 3)
+        hi = rng.uniform(0.6, 1.0, 3)
+        return {"kind": "box", "params": np.concatenate([lo, hi])}, 1.0
+    if kind == "sphere":
+        r = rng.uniform(0.7, 1.2)
+        return {"kind": "sphere", "params": np.array([0.0, 0.0, 0.0, r])}, r
+    r = rng.uniform(0.6, 1.0)
+    return {"kind": "cylinder", "params": np.array([0.0, 0.0, r, -0.8, 0.8])}, r
+
+
+def case(seed):
+    rng = np.random.default_rng(9000 + seed)
+    kind = ["gaussian", "linear", "luneburg", "fiber", "homogeneous"][seed % 5]
+    n_amb = float(rng.choice([1.0, 1.0, 1.33]))
+    if kind == "luneburg":
+        R = rng.uniform(0.8, 1.2)
+        bnd = {"kind": "sphere", "params": np.array([0.0, 0.0, 0.0, R])}
+        spec = {"kind": "luneburg", "params": np.array([R, 0.0, 0.0, 0.0]), "boundary": bnd,
+                "n_amb": 1.0}
+        return spec, R
+    if kind == "fiber":
+        R = rng.uniform(0.6, 1.0)
+        nc, Dl = rng.uniform(1.4, 1.7), rng.uniform(0.05, 0.3)
+        bnd = {"kind": "cylinder", "params": np.array([0.0, 0.0, R, -0.8, 0.8])}
+        spec = {"kind": "fiber", "params": np.array([nc, Dl, R, 0.0, 0.0]), "boundary": bnd,
+                "n_amb": n_amb}
+        return spec, R
+    bnd, size = surface(rng, ["box", "sphere", "cylinder"][seed % 3])
+    if kind == "gaussian":
+        K = int(rng.integers(1, 9))
+        n0 = rng.uniform(1.4, 1.7)
+        bumps = []
+        for _ in range(K):
+            bumps += [rng.uniform(-0.15, 0.15), rng.uniform(0.08, 0.4), *rng.uniform(-0.5, 0.5, 3)]
+        params = np.array([n0, K, *bumps])
+        params = params.astype(np.float32).astype(np.float64)
+        params[1] = K
+    elif kind == "linear":
+        params = np.array([rng.uniform(1.4, 1.7), *rng.uniform(-0.15, 0.15, 3)])
+    else:
+        params = np.array([rng.uniform(1.2, 2.0)])
+    return {"kind": kind, "params": params, "boundary": bnd, "n_amb": n_amb}, size
+
+
+def outside_rays(n, seed, size):
+    """Launch points on a sphere of radius 2.5 size, aimed at points uniform in
+    the cube of half-width 0.7 size (float32-exact)."""
+    rng = np.random.default_rng(7000 + seed)
+    v = rng.standard_normal((n, 3))
+    P0 = 2.5 * size * v / np.linalg.norm(v, axis=1)[:, None]
+    T = rng.uniform(-0.7 * size, 0.7 * size, (n, 3))
+    d0 = T - P0
+    d0 /= np.linalg.norm(d0, axis=1)[:, None]
+    return P0.astype(np.float32).astype(np.float64), d0.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("seed", range(N_CASES))
+def test_random_medium_parity(vrt, ctx, orc, seed):
+    import torch
+
+    spec, size = case(seed)
+    rays = outside_rays(1000, seed, size)
+    prm = {"dL0": 2e-3, "max_steps": 20000, "crit_rad": 1e-6, "tie_eps": 1e-7}
+    o = orc.trace(spec, rays, prm)
+    med = vrt.Medium(ctx, spec)
+    try:
+        for precision in ("fp64", "fp32c"):
+            b = vrt.RayBatch(rays[0], rays[1], precision)
+            vrt.trace(med, b, prm, precision)
+            torch.cuda.synchronize()
+            g = b.results()
+            if precision == "fp64":
+                rep = compare(o, g, aperture=2.0 * size, spec=spec)
+            else:
+                bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-7, tol=1e-5, turn=1e-7)
+                assert bad.sum() <= 0.10 * len(bad)
+                rep = compare(exempt(o, bad), exempt(g, bad), aperture=2.0 * size, spec=spec)
+                rep["ill_conditioned"] = int(bad.sum())
+            print(f"\n[random {seed} {spec['kind']} in {spec['boundary']['kind']} {precision}] "
+                  f"status {np.bincount(o['status'], minlength=6).tolist()} "
+                  f"TIR {int(o['ntir'].sum())} bTIR {int(o['nbtir'].sum())} "
+                  f"pos_err_max {rep['pos_err_max']:.2e} soft {rep['soft_flips']}", flush=True)
+            assert_parity(rep)
+    finally:
+        med.close()
