@@ -203,7 +203,8 @@ int vrt_medium_destroy(vrt_medium_t m);
 int vrt_medium_device_bytes(vrt_medium_t m, size_t *out);
 
 /* Trace n_rays rays (asynchronous on `stream`).  n_rays may be 0 (no-op).
- * Errors (nothing is launched): EINVAL for null/misaligned pointers, dL0 <= 0,
+ * Errors (nothing is launched): EINVAL for null or misaligned pointers, pointers
+ * to pageable host memory (the arrays must be device, managed or pinned), dL0 <= 0,
  * max_steps <= 0, max_lanes < 0 (or != 0 with VRT_FP64), unknown precision,
  * n_rays >= 2^31, and for VRT_FP32_COMP in a Gaussian-sum medium a dL0 above
  * 0.05 n_min sigma_min (the single-precision index difference is kept to its

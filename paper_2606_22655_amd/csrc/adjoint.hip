@@ -206,6 +206,13 @@ extern "C" int vrt_grid_loss_grad(vrt_medium_t grid, const vrt_trace_params *p,
     for (const void *q : ptrs)
         if (!q || ((uintptr_t)q & 7))
             return fail(VRT_EINVAL, "vrt_grid_loss_grad: ray array NULL or misaligned");
+    for (const void *q : ptrs)
+        if (!gpu_accessible(q))
+            return fail(VRT_EINVAL, "vrt_grid_loss_grad: a ray array is pageable host memory");
+    if ((grad && !gpu_accessible(grad)) || (rays->end && !gpu_accessible(rays->end)) ||
+        (rays->loss_ray && !gpu_accessible(rays->loss_ray)))
+        return fail(VRT_EINVAL,
+                    "vrt_grid_loss_grad: grad, end or loss_ray is pageable host memory");
     int rc = set_device(grid->ctx);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;

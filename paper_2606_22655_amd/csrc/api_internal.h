@@ -15,6 +15,9 @@ namespace vrt {
 
 // Record a message for vrt_last_error() (thread-local) and return code.
 int fail(int code, const char *fmt, ...);
+// device, managed or pinned host memory (a kernel may touch it); false for
+// pageable host memory
+bool gpu_accessible(const void *p);
 int fail_hip(hipError_t e, const char *what);
 
 }  // namespace vrt

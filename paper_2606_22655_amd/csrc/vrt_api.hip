@@ -34,6 +34,18 @@ int vrt::fail_hip(hipError_t e, const char *what) {
                 hipGetErrorString(e));
 }
 
+// A kernel may read or write this pointer: device, managed or pinned host
+// memory.  Pageable host memory is refused (a kernel touching it would take a
+// memory fault).
+bool vrt::gpu_accessible(const void *p) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type != hipMemoryTypeUnregistered;
+}
+
 static int dev_alloc(vrt_medium_t m, void **p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) return fail_hip(e, "hipMalloc (medium)");
@@ -495,6 +507,7 @@ int vrt_medium_device_bytes(vrt_medium_t m, size_t *out) {
 
 static bool aligned(const void *p, size_t a) { return p && ((uintptr_t)p % a) == 0; }
 
+
 // Argument checks shared by vrt_trace and vrt_trace_paths.
 static int check_trace_args(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays,
                             size_t n_rays, const char *who) {
@@ -524,6 +537,14 @@ static int check_trace_args(vrt_medium_t m, const vrt_trace_params *p, const vrt
     const void *uptrs[] = {rays->status, rays->steps, rays->n_tir, rays->n_btir, rays->flags};
     for (const void *q : uptrs)
         if (!aligned(q, 4)) return fail(VRT_EINVAL, "%s: result array NULL or misaligned", who);
+    for (const void *q : ptrs)
+        if (!gpu_accessible(q))
+            return fail(VRT_EINVAL, "%s: a ray array is pageable host memory (not GPU-accessible)",
+                        who);
+    for (const void *q : uptrs)
+        if (!gpu_accessible(q))
+            return fail(VRT_EINVAL,
+                        "%s: a result array is pageable host memory (not GPU-accessible)", who);
     return VRT_OK;
 }
 
@@ -594,6 +615,8 @@ int vrt_trace_paths(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *r
     if (n_rays == 0) return VRT_OK;
     if (!aligned(path, 8) || !aligned(n_points, 8))
         return fail(VRT_EINVAL, "vrt_trace_paths: path or n_points NULL or misaligned");
+    if (!gpu_accessible(path) || !gpu_accessible(n_points))
+        return fail(VRT_EINVAL, "vrt_trace_paths: path or n_points is pageable host memory");
     int rc = set_device(m->ctx);
     if (rc) return rc;
     LaunchArgs a{};

@@ -385,6 +385,45 @@ def test_full_size_sampled_parity(vrt, ctx, orc):
     assert_parity(rep)
 
 
+def test_pageable_host_arrays_are_refused(vrt, ctx):
+    """Ray arrays in pageable host memory are refused before any launch (a
+    kernel touching them would fault); pinned host memory is accepted."""
+    import ctypes as C
+
+    import torch
+
+    spec, (P0, d0), prm = workloads.gaussian_cube(n_rays=64)
+    med = vrt.Medium(ctx, spec)
+    try:
+        host = [np.zeros(64, dtype=np.float32) for _ in range(12)]
+        u32 = [np.zeros(64, dtype=np.uint32) for _ in range(5)]
+        r = vrt.vrt_rays()
+        for a, k in zip(host, ("px", "py", "pz", "dx", "dy", "dz", "ox", "oy", "oz", "odx", "ody",
+                               "odz")):
+            setattr(r, k, a.ctypes.data_as(C.c_void_p).value)
+        for a, k in zip(u32, ("status", "steps", "n_tir", "n_btir", "flags")):
+            setattr(r, k, a.ctypes.data_as(C.c_void_p).value)
+        stream = torch.cuda.current_stream().cuda_stream
+        with pytest.raises(vrt.VrtError, match="pageable"):
+            vrt.vrt_trace(med.handle, vrt.make_params(prm, "fp32c"), r, 64, stream)
+        # one device array swapped in is not enough
+        b = vrt.RayBatch(P0, d0, "fp32c")
+        b.rays.oz = host[8].ctypes.data_as(C.c_void_p).value
+        with pytest.raises(vrt.VrtError, match="pageable"):
+            vrt.vrt_trace(med.handle, vrt.make_params(prm, "fp32c"), b.rays, 64, stream)
+        # pinned host outputs are GPU-accessible and accepted
+        pinned = torch.empty((6, 64), dtype=torch.float32, pin_memory=True)
+        b2 = vrt.RayBatch(P0, d0, "fp32c")
+        for i, k in enumerate(("ox", "oy", "oz", "odx", "ody", "odz")):
+            setattr(b2.rays, k, pinned[i].data_ptr())
+        vrt.vrt_trace(med.handle, vrt.make_params(prm, "fp32c"), b2.rays, 64, stream)
+        torch.cuda.synchronize()
+        ref = run_gpu(vrt, ctx, spec, (P0, d0), prm, "fp32c")
+        assert np.array_equal(pinned[0:3].numpy().T.astype(np.float64), ref["P"])
+    finally:
+        med.close()
+
+
 def test_api_errors(vrt, ctx):
     import torch
 
