@@ -419,6 +419,9 @@ int vrt_medium_create_grid(vrt_context_t ctx, const float *values, int nx, int n
         return fail(VRT_EINVAL, "grid extent needs finite lo < hi");
     if (!(n_ambient > 0.0) || !isfinite(n_ambient))
         return fail(VRT_EINVAL, "n_ambient must be finite and > 0");
+    if (values_on_device && !gpu_accessible(values))
+        return fail(VRT_EINVAL, "vrt_medium_create_grid: values_on_device set for pageable host "
+                                "memory");
     int rc = set_device(ctx);
     if (rc) return rc;
     auto *m = new vrt_medium_s();
