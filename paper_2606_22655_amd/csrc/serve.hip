@@ -71,7 +71,11 @@ constexpr uint32_t kSlots = 4096;       // job table ring
 constexpr size_t kDescBytes = 1024;     // one descriptor slot
 constexpr uint32_t kIdlePolls = 40;     // empty polls (backing off to ~55 us apart) before leaving
 constexpr uint32_t kLingerPolls = 20000;  // ~1 s of empty polls: leave even with jobs live
-constexpr uint32_t kDryEvery = 64;      // iterations between tail reads of a wave whose group ran dry
+// iterations (~2 ms) between tail reads of a wave whose group ran dry: the
+// words read are the same few lines for every wave, and polled every 64
+// iterations they queue up enough to slow grid jobs, whose long rays keep
+// dry waves busy, by a fifth
+constexpr uint32_t kDryEvery = 1024;
 constexpr uint64_t kPollTicks = 200;    // 2 us at the 100 MHz wall clock between host-tail polls
 constexpr int kRanges = 4;              // job ranges one refill may draw from
 constexpr uint32_t kScan = 64;          // jobs a refill looks ahead for its group
