@@ -316,6 +316,9 @@ __device__ __attribute__((noinline)) void march_group(WaveCtx &cw, LdsDesc Dp, L
         if (nm && !dry) {
             const uint32_t want = (uint32_t)__popcll(nm);
             const int leader = __ffsll((unsigned long long)nm) - 1;
+            // the wave marches a ray of job jcur: that job is not done, so its
+            // slot still holds it, and it is of the wave's group
+            const bool hold = __ballot(active && lslot == c.jcur % kSlots) != 0;
             uint32_t r0 = 0, b0 = 0, c0 = 0, r1 = 0, b1 = 0, c1 = 0, r2 = 0, b2 = 0, c2 = 0,
                      r3 = 0, b3 = 0, c3 = 0, nr = 0, jc = c.jcur, unmet = 0;
             if (c.lane == leader) {
@@ -326,10 +329,14 @@ __device__ __attribute__((noinline)) void march_group(WaveCtx &cw, LdsDesc Dp, L
                 for (uint32_t jj = c.jcur; need && jj < lim && nr < (uint32_t)kRanges; ++jj) {
                     const uint32_t sl = jj % kSlots;
                     const uint32_t nj = c.table[sl].n;
-                    const unsigned long long w =
-                        __hip_atomic_load(&c.ctl[sl].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    bool gone = (uint32_t)(w >> 32) != jj || (uint32_t)w >= nj;
-                    if (!gone && c.table[sl].group == group) {
+                    const bool held = hold && jj == c.jcur;
+                    bool gone = false;
+                    if (!held) {
+                        const unsigned long long w = __hip_atomic_load(
+                            &c.ctl[sl].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        gone = (uint32_t)(w >> 32) != jj || (uint32_t)w >= nj;
+                    }
+                    if (!gone && (held || c.table[sl].group == group)) {
                         // one fetch-and-add (a compare-and-swap loop here stalls every
                         // wave on one contended word); an add past the end only takes
                         // what is left, and n < 2^31 keeps the overshoot out of the
