@@ -40,6 +40,13 @@ MUTATIONS = {
     "fiber_grad_sign": ("double k = -2.0 * Dl * nc * nc / (R * R * nv);",
                         "double k = 2.0 * Dl * nc * nc / (R * R * nv);"),
     "box_exit_face_swapped": ("bf = R[a] > 0.0 ? a + 3 : a;", "bf = R[a] > 0.0 ? a : a + 3;"),
+    "grid_interior_forward_difference": (
+        "        lo[axis] = idx[axis] - 1;\n        hi[axis] = idx[axis] + 1;\n        span = 2.0 * h;",
+        "        hi[axis] = idx[axis] + 1;\n        span = h;"),
+    "tie_distance_along_ray": ("double dist = fabs(tx - Delta) * fabs(dot3(R, Ne));",
+                               "double dist = fabs(tx - Delta);"),
+    "grazing_window_mu_above_one": ("if (mu < 1.0 && fabs(c) < 10.0 * q->crit_rad) {",
+                                    "if (mu > 1.0 && fabs(c) < 10.0 * q->crit_rad) {"),
 }
 
 PINS = [getattr(pins, n) for n in dir(pins) if n.startswith("test_")]

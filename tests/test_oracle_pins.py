@@ -635,3 +635,154 @@ def test_exit_gain_is_the_derivative_of_snells_law():
     # not on the surface (an exit plane) or not exited: no widening
     orc_p = {"status": np.array([0, 2, 0, 0], np.uint32), "P": P + [0, 0, 0.5], "D": D}
     assert np.all(exit_gain(spec, orc_p, lambda Q: np.full(len(Q), n_in)) == 1.0)
+
+
+# ---------------------------------------------------------------------------
+# the grid's node gradient at interior nodes (discretized-medium reading:
+# central differences inside, one-sided at the faces)
+# ---------------------------------------------------------------------------
+def _quadratic_grid(N=9):
+    """Nodes k/(N-1) of the unit cube carrying a full quadratic field whose
+    node values are exact in float32 (coefficients and coordinates are short
+    dyadic fractions), with its analytic gradient."""
+    a, b, c, d, e, f = 0.0625, -0.125, 0.09375, 0.03125, -0.046875, 0.0546875
+    gx0, gy0, gz0 = 0.25, -0.1875, 0.125
+
+    def q(X, Y, Z):
+        return (1.5 + gx0 * X + gy0 * Y + gz0 * Z + a * X * X + b * Y * Y + c * Z * Z +
+                d * X * Y + e * Y * Z + f * X * Z)
+
+    def grad(X, Y, Z):
+        return np.stack([gx0 + 2 * a * X + d * Y + f * Z,
+                         gy0 + 2 * b * Y + d * X + e * Z,
+                         gz0 + 2 * c * Z + e * Y + f * X], axis=-1)
+
+    k = np.arange(N) / (N - 1)
+    Z, Y, X = np.meshgrid(k, k, k, indexing="ij")
+    vals = q(X, Y, Z)
+    assert np.array_equal(vals.astype(np.float32).astype(np.float64), vals)
+    return workloads.grid_medium(vals.astype(np.float32)), q, grad, (a, b, c)
+
+
+def test_grid_gradient_is_exact_for_a_quadratic_field_inside(orc):
+    """Central differences are exact for a quadratic, so at every point of a
+    cell whose eight corners are interior nodes the gradient (trilinear blend
+    of the node differences, each exact and linear in the coordinates) equals
+    the analytic one.  A one-sided (forward or backward) stencil is off by
+    a h there, which this rules out."""
+    N = 9
+    grid, q, grad, (a, b, c) = _quadratic_grid(N)
+    h = 1.0 / (N - 1)
+    rng = np.random.default_rng(31)
+    pts = rng.uniform(h, 1.0 - h, (300, 3))
+    n, g = orc.evaluate(grid, pts)
+    assert np.allclose(g, grad(pts[:, 0], pts[:, 1], pts[:, 2]), rtol=0, atol=1e-13)
+    # at the interior nodes themselves, n is the node value
+    k = np.arange(1, N - 1) * h
+    Z, Y, X = np.meshgrid(k, k, k, indexing="ij")
+    nodes = np.column_stack([X.ravel(), Y.ravel(), Z.ravel()])
+    nn, gn = orc.evaluate(grid, nodes)
+    assert np.allclose(nn, q(nodes[:, 0], nodes[:, 1], nodes[:, 2]), rtol=0, atol=1e-15)
+    assert np.allclose(gn, grad(nodes[:, 0], nodes[:, 1], nodes[:, 2]), rtol=0, atol=1e-13)
+
+
+def test_grid_gradient_is_one_sided_at_the_faces(orc):
+    """At a face node the difference runs over the one spacing that exists:
+    (q(h) - q(0)) / h = q'(0) + a h for the pure square term, and
+    (q(1) - q(1-h)) / h = q'(1) - a h on the opposite face."""
+    N = 9
+    grid, q, grad, (a, b, c) = _quadratic_grid(N)
+    h = 1.0 / (N - 1)
+    y, z = 3 * h, 5 * h
+    lo_face, hi_face = np.array([[0.0, y, z]]), np.array([[1.0, y, z]])
+    _, g_lo = orc.evaluate(grid, lo_face)
+    _, g_hi = orc.evaluate(grid, hi_face)
+    ex_lo = grad(0.0, y, z)[0] + a * h
+    ex_hi = grad(1.0, y, z)[0] - a * h
+    assert abs(g_lo[0, 0] - ex_lo) < 1e-13 and abs(g_hi[0, 0] - ex_hi) < 1e-13
+    # the other two components at those nodes are interior central differences
+    assert np.allclose(g_lo[0, 1:], grad(0.0, y, z)[1:], atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# the windows that mark ill-conditioned decisions, placed by hand
+# ---------------------------------------------------------------------------
+def _tie_case(orc, boundary, E, X, d, cos_t, delta_perp, k=5, dL0=1e-3, n=1.5):
+    """Launch a ray inside a homogeneous medium so that the end of its k-th
+    constant-OPL step lies at signed distance delta_perp from the surface,
+    measured perpendicular to it (> 0: inside).  E is where the step ends, X the
+    surface point on the ray.  Returns the oracle's flags after the ray meets
+    the surface (the march is truncated right after the surface event)."""
+    med = homogeneous(n, boundary)
+    Delta = dL0 / n
+    P0 = E - k * Delta * d
+    r = orc.trace(med, (P0[None], d[None]), P(dL0, max_steps=k + 1))
+    return int(r["flags"][0]), r
+
+
+def test_near_tie_window_is_perpendicular_distance_box(orc):
+    """Sec. II case (i): whether a step is cut at the surface or taken in full
+    is decided by the step end's side of the surface.  The near-tie flag marks
+    a step end within tie_eps of the surface measured perpendicular to it, so
+    a ray crossing the face z = 1 at cos t = 1/4 is flagged at a perpendicular
+    distance of tie_eps / 2 (two tie_eps along the ray) on either side, and
+    not at 2 tie_eps; the ten times wider bit marks 5 tie_eps."""
+    tie = workloads.DEFAULT_TIE_EPS
+    cos_t = 0.25
+    d = np.array([math.sqrt(1.0 - cos_t * cos_t), 0.0, cos_t])
+    bnd = box((0, 0, 0), (1, 1, 1))
+    for dp, narrow, wide in ((0.5 * tie, True, True), (-0.5 * tie, True, True),
+                             (2 * tie, False, True), (-2 * tie, False, True),
+                             (5 * tie, False, True), (20 * tie, False, False)):
+        X = np.array([0.2, 0.5, 1.0])
+        E = X - (dp / cos_t) * d
+        flags, r = _tie_case(orc, bnd, E, X, d, cos_t, dp)
+        assert bool(flags & orc.F_NEAR_TIE) == narrow, dp
+        assert bool(flags & orc.F_NEAR_TIE_WIDE) == wide, dp
+        # the geometry is what was built: the ray meets the face after 5 or 6 steps
+        assert r["nbtir"][0] == 1 and r["status"][0] == orc.TRUNCATED
+
+
+def test_near_tie_window_is_perpendicular_distance_sphere(orc):
+    """The same construction at the unit sphere: the step end sits at
+    perpendicular distance dp from the surface point X where the ray crosses,
+    with N(X) . d = 1/4."""
+    tie = workloads.DEFAULT_TIE_EPS
+    cos_t = 0.25
+    N = np.array([0.36, -0.48, 0.8])  # unit
+    t = np.cross(N, [0.0, 0.0, 1.0])
+    t /= np.linalg.norm(t)
+    d = cos_t * N + math.sqrt(1 - cos_t * cos_t) * t
+    for dp, narrow in ((0.5 * tie, True), (-0.5 * tie, True), (2 * tie, False),
+                       (-2 * tie, False)):
+        X = N.copy()
+        E = X - (dp / cos_t) * d
+        flags, r = _tie_case(orc, sphere(1.0), E, X, d, cos_t, dp)
+        assert bool(flags & orc.F_NEAR_TIE) == narrow, dp
+        assert r["nbtir"][0] == 1
+
+
+def test_near_grazing_window_into_higher_index(orc):
+    """Eq. (10) takes sgn(N.I): a ray entering higher index (mu < 1) nearly
+    along the isoindicial surface is refracted to one side of it or the other
+    by the sign of a tiny N.I.  In the stratified medium n = 1.5 + 0.2 z
+    (N = z) a ray launched inside with I_z = s takes a first step with mu = 1
+    (no bend) and meets its second decision with mu = n(P_0)/n(P_1) < 1 and
+    N.I = s exactly.  Flagged for |s| < crit_rad, also at ten times that in
+    the wide bit; a ray going down (mu > 1) is a TIR case, never flagged as
+    grazing."""
+    crit = workloads.DEFAULT_CRIT_RAD
+    med = linear_slab(1.5, 0.2)
+    for s, narrow, wide in ((0.5 * crit, True, True), (2 * crit, False, True),
+                            (5 * crit, False, True), (20 * crit, False, False),
+                            (-0.5 * crit, False, False)):
+        d = np.array([[math.sqrt(1.0 - s * s), 0.0, s]])
+        P0 = np.array([[0.3, 0.5, 0.5]])
+        r = orc.trace(med, (P0, d), P(1e-3, max_steps=2))
+        f = int(r["flags"][0])
+        assert bool(f & orc.F_NEAR_GRAZING) == narrow, s
+        assert bool(f & orc.F_NEAR_GRAZING_WIDE) == wide, s
+        if s < 0:
+            assert r["ntir"][0] == 1  # mu > 1 at grazing: reflected, Eq. (19)
+        else:
+            assert r["ntir"][0] == 0
