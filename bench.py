@@ -219,9 +219,12 @@ def cpu_baseline(spec, rays, prm, sample, g_res, aperture):
     rep = compare(r, sub, aperture=aperture, spec=spec)
     if chaotic:
         rep["ill_conditioned"] = int(bad.sum())
-    keys = ("n", "flagged_oracle", "flagged_gpu", "soft_flips", "status_mismatch", "tir_mismatch",
-            "btir_mismatch", "pos_fail", "dir_fail", "steps_mismatch", "pos_err_max", "pos_err_p99",
-            "dir_err_max", "dir_err_p99", "dir_err_inside_max", "ill_conditioned")
+    keys = ("n", "checked", "fail", "exempt_critical", "exempt_grazing", "tie_checked",
+            "tie_steps_differ", "flagged_oracle_critical", "flagged_oracle_tie",
+            "flagged_oracle_grazing", "flagged_gpu_critical", "status_mismatch", "tir_mismatch",
+            "btir_mismatch", "pos_fail", "dir_fail", "fail_in_wide_window", "steps_mismatch",
+            "steps_absmax", "pos_err_max", "pos_err_p99", "dir_err_max", "dir_err_p99",
+            "dir_err_inside_max", "ill_conditioned", "bad_rays")
     return base, {k: rep[k] for k in keys if k in rep}
 
 

@@ -187,16 +187,24 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
  * bounded by the box [lo, hi] in surroundings of index n_ambient.  Between
  * nodes n is the trilinear interpolant and grad n the trilinear interpolant
  * of the node central differences (one-sided at the first and last node).
- * `values` is a host pointer if values_on_device == 0, else a device pointer;
- * it is copied either way.  Each dimension must be >= 2 and <= 4096.
+ * `values` is a host pointer if values_on_device == 0, else a device pointer
+ * whose contents must be complete when the call is made (the copy runs on the
+ * library's own stream, not the caller's); it is copied either way and the
+ * call returns once the medium is ready.  Each dimension must be >= 2 and
+ * <= 4096.
  * Errors: EINVAL (sizes, non-positive or non-finite values, lo >= hi),
  * ENOMEM, EHIP. */
 int vrt_medium_create_grid(vrt_context_t ctx, const float *values, int nx, int ny, int nz,
                            const double lo[3], const double hi[3], double n_ambient,
                            int values_on_device, vrt_medium_t *out);
 
-/* Destroy a medium.  Waits for the device to finish work issued on it
- * (device-wide synchronisation) before freeing.  Errors: EINVAL. */
+/* Destroy a medium.  Returns without waiting: its device memory is freed in
+ * stream order on the library's own stream once every eager vrt_trace /
+ * vrt_trace_paths launched on it has completed (the library records an event
+ * per stream after each launch).  Launches captured in a graph are not
+ * tracked: the owner of the graph must not replay it after destroying a
+ * medium it reads.  Errors: EINVAL (NULL, or serving jobs on the medium not
+ * yet done). */
 int vrt_medium_destroy(vrt_medium_t m);
 
 /* Device memory held by the medium, in bytes. */
@@ -209,7 +217,14 @@ int vrt_medium_device_bytes(vrt_medium_t m, size_t *out);
  * n_rays >= 2^31, and for VRT_FP32_COMP in a Gaussian-sum medium a dL0 above
  * 0.05 n_min sigma_min (the single-precision index difference is kept to its
  * stated accuracy only below that); EUNSUPPORTED for combinations this library version
- * does not implement; EHIP for launch failures. */
+ * does not implement; EHIP for launch failures; ENOMEM when a trace is captured in a
+ * graph and the context has no queue slot left for it.
+ * Concurrency: traces may run on any streams at once.  A VRT_FP32_COMP launch
+ * takes a ray-queue counter from the context: eager launches share 64 recycled
+ * counters, each guarded by an event (a launch waits on its stream for the
+ * counter's previous launch); a launch captured in a graph keeps a counter of
+ * its own for the context's life (960 of them), so replays never share one
+ * with any other launch. */
 int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, size_t n_rays,
               void *stream);
 

@@ -215,6 +215,11 @@ def vrt_n2p_sweep(lens, beta_gamma, y, z_launch, params, stream=0, want_z=False,
                   want_steps=False):
     """RMSE_LSA per (beta, gamma) candidate, then (if asked) the axis
     crossings (n_cand, n_rays) and the ray-steps per candidate."""
+    return _sweep(load_library().vrt_n2p_sweep, lens, beta_gamma, y, z_launch, params, stream,
+                  want_z, want_steps)
+
+
+def _sweep(fn, lens, beta_gamma, y, z_launch, params, stream, want_z, want_steps):
     import numpy as np
 
     bg = np.ascontiguousarray(beta_gamma, dtype=np.float64).reshape(-1, 2)
@@ -223,7 +228,7 @@ def vrt_n2p_sweep(lens, beta_gamma, y, z_launch, params, stream=0, want_z=False,
     z = np.zeros((bg.shape[0], yy.size)) if want_z else None
     st = np.zeros(bg.shape[0], dtype=np.uint64) if want_steps else None
     dp = C.POINTER(C.c_double)
-    _check(load_library().vrt_n2p_sweep(
+    _check(fn(
         lens, bg.ctypes.data_as(dp), bg.shape[0], yy.ctypes.data_as(dp), yy.size,
         float(z_launch), C.byref(params), rmse.ctypes.data_as(dp),
         z.ctypes.data_as(dp) if want_z else None,
@@ -344,7 +349,10 @@ class Medium:
 
 
 def _grid_from_device(ctx, values, lo, hi, n_amb):
-    """A grid medium built on the device from a (nz, ny, nx) float32 CUDA tensor."""
+    """A grid medium built on the device from a (nz, ny, nx) float32 CUDA tensor
+    (the library copies it on its own stream: the tensor's writes on the current
+    stream must be complete first)."""
+    _torch().cuda.current_stream().synchronize()
     nz, ny, nx = values.shape
     return vrt_medium_create_grid(ctx.handle, values.data_ptr(), nx, ny, nz, lo, hi, n_amb, 1)
 

@@ -28,7 +28,13 @@ int fail_hip(hipError_t e, const char *what);
         if (e_ != hipSuccess) return ::vrt::fail_hip(e_, (what));  \
     } while (0)
 
+// Ray-queue counters of the single-precision batch kernel.  The first
+// kEagerSlots are recycled round-robin by eager launches, each guarded by an
+// event: a launch that takes a slot first makes its stream wait for the slot's
+// previous launch.  A launch captured in a graph takes one of the other slots
+// for good (the graph replays on it), so no eager launch ever shares it.
 static constexpr int kQueueSlots = 1024;
+static constexpr int kEagerSlots = 64;
 static constexpr int kQueueStride = 16;  // uint32 per slot: one 64-byte line each
 static constexpr int kNumCounters = 15;
 
@@ -37,10 +43,22 @@ struct vrt_context_s {
     int num_cu = 256;
     uint32_t *queues = nullptr;  // kQueueSlots ray-queue counters
     unsigned long long *counters = nullptr;
-    std::atomic<uint32_t> next_slot{0};
+    hipStream_t aux = nullptr;   // library stream: medium uploads and stream-ordered frees
+    std::mutex slot_mu;          // guards the slot state below
+    hipEvent_t slot_ev[kEagerSlots] = {};
+    bool slot_recorded[kEagerSlots] = {};
+    uint32_t next_eager = 0;
+    uint32_t n_captured = 0;     // slots given to captured launches
+    bool async_pools = false;    // the device has the stream-ordered allocator
     std::atomic<int> n_media{0};
     std::atomic<int> n_servers{0};
     std::mutex counters_mu;
+};
+
+// The last launch on a medium from one stream (its event), for the deferred free.
+struct MediumUse {
+    hipStream_t stream;
+    hipEvent_t ev;
 };
 
 struct vrt_medium_s {
@@ -51,6 +69,9 @@ struct vrt_medium_s {
     vrt::BoundaryDev bnd{};
     size_t bytes = 0;
     std::vector<void *> allocs;
+    bool async_allocs = true;  // allocs come from the stream-ordered allocator
+    std::mutex use_mu;
+    std::vector<MediumUse> uses;  // eager launches that may still read the medium
     std::atomic<int> jobs{0};  // server jobs submitted on it and not yet done
 };
 

@@ -20,6 +20,14 @@
 //     gamma = -sgn(c) (mu-1)(mu+1) / (sqrt(D) + mu |c|), the same root as
 //     Eq. (10) without its cancellation;
 //   - position and direction are Kahan-compensated float pairs (value = h - c);
+//   - the step length Delta = dL0 / n is a float pair (Dh + Dl) formed from
+//     dL0 and n as float pairs with one Newton correction, and each move adds
+//     Delta I to the position with the product's rounding error, the
+//     direction's compensation term and Dl folded into the compensation: a
+//     float-rounded step length or a move along the rounded direction alone
+//     biases every step the same way (dL0 = 5e-4 rounds 2.5e-8 short), and the
+//     drift along the path shifts where the discrete TIR of a turning point
+//     lands, which moves the reflected direction by ~1e-6 rad;
 //   - the discriminant D = mu^2 c^2 - (mu^2 - 1) is evaluated in double;
 //   - near grazing incidence, c^2 <= 4 |mu^2 - 1| -- the only region where a
 //     refraction/TIR decision can be taken or where gamma is sensitive to the
@@ -52,6 +60,25 @@ __device__ __forceinline__ void split(double v, float &h, float &c) {
     h = (float)v;
     c = (float)((double)h - v);
 }
+// Step length Delta = (dh + dl) / (nh + nl) as Dh + Dl (the low parts are
+// far below the high ones): a quotient from the hardware reciprocal, its
+// exact residual dh - q nh (fma), the low parts' first-order terms, and one
+// Newton correction.  Relative error ~1e-13.
+__device__ __forceinline__ void step_len(float dh, float dl, float nh, float nl, float &Dh,
+                                         float &Dl) {
+    const float r = __builtin_amdgcn_rcpf(nh);
+    const float q = dh * r;
+    float e = __builtin_fmaf(-q, nh, dh);
+    e = __builtin_fmaf(-q, nl, e + dl);
+    const float c = e * r;
+    Dh = q + c;
+    Dl = (q - Dh) + c;
+}
+// Step length in double as Dh + Dl.
+__device__ __forceinline__ void step_len64(double v, float &Dh, float &Dl) {
+    Dh = (float)v;
+    Dl = (float)(v - (double)Dh);
+}
 
 // Discretized medium: cached records of the 8 corners of the current cell.
 struct GridCache {
@@ -66,7 +93,7 @@ struct Lane {
     float nlb;                           // n(P_{i-1}) = nlb + nld (grid: cell base value
     double nld;                          //   + offset inside the cell; media taken in double:
                                          //   the double index split; other media: nld = 0)
-    float Delta;                         // pending move length
+    float Delta, Dl;                     // pending move length Delta + Dl
     uint32_t r, steps, ntir, nbtir, flags;
     bool pending;                        // R = I and Delta set by an event: move without deciding
 };
@@ -282,7 +309,7 @@ __device__ bool lane_init(const MediumDev &m, const float4 *__restrict__ rec, co
     split(R.y, L.Ihy, L.Icy);
     split(R.z, L.Ihz, L.Icz);
     index_at_event<MK>(m, rec, gc, P, L.nlb, L.nld);
-    L.Delta = (float)(t.dL0 / n_in);
+    step_len64(t.dL0 / n_in, L.Delta, L.Dl);
     L.pending = true;
     return true;
 }
@@ -296,13 +323,15 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
                                           GridCache &gc, float dL0, float eps_tan, float mrg,
                                           float crit_f) {
     if (!L.pending) {
-        float ni, gx, gy, gz, dn, nb = 0.f;
+        const float dL0l = (float)(t.dL0 - (double)dL0);  // dL0 = dL0 + dL0l
+        float ni, gx, gy, gz, dn, nb = 0.f, nl = 0.f;
         double nd = 0.0;
         float n_last = L.nlb;  // float-evaluated analytic media keep nld = 0
         if constexpr (MK == VRT_MEDIUM_GRID) n_last = (float)((double)L.nlb + L.nld);
         if constexpr (MK == VRT_MEDIUM_GRID) {
             grid32(m, rec, gc, L.Phx, L.Phy, L.Phz, L.Pcx, L.Pcy, L.Pcz, L.nlb, L.nld, ni, nb, nd, gx,
                    gy, gz, dn);
+            nl = (float)(((double)nb + nd) - (double)ni);
         } else if constexpr (kIndexIn64<MK>) {
             // n and grad n in double at the compensated position; n(P_{i-1}) is
             // kept as nlb + nld, so dn is a difference of two double indices
@@ -312,6 +341,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
             med64<MK>(m, P64, n64, g64);
             ni = nb = (float)n64;
             nd = n64 - (double)nb;
+            nl = (float)nd;
             dn = (float)(n64 - ((double)L.nlb + L.nld));
             gx = (float)g64.x;
             gy = (float)g64.y;
@@ -320,16 +350,16 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
         } else {
             f3 g;
             med32<MK>(m, mf, bumps, dL0, mkf(L.Phx, L.Phy, L.Phz), mkf(L.sx, L.sy, L.sz), n_last,
-                      ni, g, dn);
+                      ni, nl, g, dn);
             gx = g.x;
             gy = g.y;
             gz = g.z;
             nb = ni;
         }
-        float incx = 0.f, incy = 0.f, incz = 0.f, Delta;
+        float incx = 0.f, incy = 0.f, incz = 0.f, Delta, Dl;
         const float gl2 = gx * gx + gy * gy + gz * gz;
         if (!(gl2 > 0.0f) || !isfinite(gl2)) {  // cases (ii)/(iii): straight
-            Delta = dL0 * frcp(ni);
+            step_len(dL0, dL0l, ni, nl, Delta, Dl);
             L.flags |= VRT_FLAG_STRAIGHT;
         } else {
             const float inv = rsqrtf(gl2);
@@ -339,7 +369,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
             if (fabsf(c) <= eps_tan) {
                 // case (iv): arc with curvature grad n / n, Eqs. (16)-(18);
                 // dn along the probe Delta N in difference form
-                Delta = dL0 * frcp(ni);
+                step_len(dL0, dL0l, ni, nl, Delta, Dl);
                 const float qx = Delta * Nx, qy = Delta * Ny, qz = Delta * Nz;
                 float np, dnp;
                 if constexpr (MK == VRT_MEDIUM_GRID) {
@@ -358,8 +388,9 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
                     dnp = (float)(nq - ((double)nb + nd));
                 } else {
                     f3 gp;
+                    float npl;
                     med32<MK>(m, mf, bumps, dL0, mkf(L.Phx + qx, L.Phy + qy, L.Phz + qz), mkf(qx, qy, qz), ni,
-                              np, gp, dnp);
+                              np, npl, gp, dnp);
                 }
                 const float a = dnp * frcp(2.0f * ni);
                 const float w = fsqrt(fmaxf(0.0f, 1.0f - a * a));
@@ -397,11 +428,11 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
                     d3 R;
                     if (D <= 0.0) {  // case (v): reflect, Delta_{i-1} (Eq. (20))
                         R = reflect64(I64, N, cd);
-                        Delta = (float)(t.dL0 / np64);
+                        step_len64(t.dL0 / np64, Delta, Dl);
                         L.ntir++;
                     } else {
                         R = snell64(I64, N, mu, cd, D);
-                        Delta = (float)(t.dL0 / ni64);
+                        step_len64(t.dL0 / ni64, Delta, Dl);
                     }
                     split(R.x, L.Ihx, L.Icx);
                     split(R.y, L.Ihy, L.Icy);
@@ -424,7 +455,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
                     incx = m1 * L.Ihx + gam * Nx;
                     incy = m1 * L.Ihy + gam * Ny;
                     incz = m1 * L.Ihz + gam * Nz;
-                    Delta = dL0 * frcp(ni);
+                    step_len(dL0, dL0l, ni, nl, Delta, Dl);
                 }
             }
         }
@@ -434,10 +465,11 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
         kahan_add(L.Ihy, L.Icy, incy);
         kahan_add(L.Ihz, L.Icz, incz);
         L.Delta = Delta;
+        L.Dl = Dl;
     }
     L.pending = false;
     // ---- move (Eqs. (3)-(4)), cut at the enclosing surface (case (i)) ----
-    const float Delta = L.Delta;
+    const float Delta = L.Delta, Dl = L.Dl;
     const float mvx = Delta * L.Ihx, mvy = Delta * L.Ihy, mvz = Delta * L.Ihz;
     bool full = surf_inside_margin(b, L.Phx + mvx, L.Phy + mvy, L.Phz + mvz, mrg);
     d3 P64, R64;
@@ -447,18 +479,27 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
         P64 = mk((double)L.Phx - L.Pcx, (double)L.Phy - L.Pcy, (double)L.Phz - L.Pcz);
         R64 = mk((double)L.Ihx - L.Icx, (double)L.Ihy - L.Icy, (double)L.Ihz - L.Icz);
         tx = surf_exit(b, P64, R64, face);
-        full = tx > (double)Delta;
-        if (tx < 3.0 * (double)Delta) {  // distance of the step end from the surface
+        const double D64 = (double)Delta + (double)Dl;
+        full = tx > D64;
+        if (tx < 3.0 * D64) {  // distance of the step end from the surface
             const d3 Ne = surf_normal(b, P64 + tx * R64, face);
-            if (fabs(tx - (double)Delta) * fabs(dot(R64, Ne)) < t.tie_eps)
+            if (fabs(tx - D64) * fabs(dot(R64, Ne)) < t.tie_eps)
                 L.flags |= VRT_FLAG_NEAR_TIE;
         }
     }
     L.steps++;
     if (full) {
+        // P += (Delta + Dl)(Ih - Ic): the float move, then its rounding error,
+        // Dl and the direction's compensation into the compensation term
+        const float ex = __builtin_fmaf(Delta, L.Ihx, -mvx) + (Dl * L.Ihx - Delta * L.Icx);
+        const float ey = __builtin_fmaf(Delta, L.Ihy, -mvy) + (Dl * L.Ihy - Delta * L.Icy);
+        const float ez = __builtin_fmaf(Delta, L.Ihz, -mvz) + (Dl * L.Ihz - Delta * L.Icz);
         kahan_add(L.Phx, L.Pcx, mvx);
         kahan_add(L.Phy, L.Pcy, mvy);
         kahan_add(L.Phz, L.Pcz, mvz);
+        L.Pcx -= ex;
+        L.Pcy -= ey;
+        L.Pcz -= ez;
         L.sx = mvx;
         L.sy = mvy;
         L.sz = mvz;
@@ -487,7 +528,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
         split(R.x, L.Ihx, L.Icx);
         split(R.y, L.Ihy, L.Icy);
         split(R.z, L.Ihz, L.Icz);
-        L.Delta = (float)(t.dL0 / n_last);
+        step_len64(t.dL0 / n_last, L.Delta, L.Dl);
         index_at_event<MK>(m, rec, gc, P, L.nlb, L.nld);
         L.nbtir++;
         L.flags |= VRT_FLAG_BOUNDARY_TIR;

@@ -315,23 +315,32 @@ template <int MK>
 constexpr bool kIndexIn64 =
     MK == VRT_MEDIUM_SPHERICAL || MK == VRT_MEDIUM_N2P || MK == VRT_MEDIUM_ZERNIKE;
 
-// P: point P_i, s = P_i - P_{i-1}, n_last = n(P_{i-1}).  bumps: the Gaussian
+// P: point P_i, s = P_i - P_{i-1}, n_last = n(P_{i-1}).  n + nl is the index
+// at P_i where the medium's constant part is split off (homogeneous, linear,
+// Gaussian: n0 exactly as given plus the float-summed variable part); nl = 0
+// for the Luneburg and fiber media.  bumps: the Gaussian
 // table (m.bumps_f) -- a restrict kernel argument in the batch kernel (its
 // loads are then scalar), a copy in LDS in the serving kernel.
-// MedF.q: LINEAR [n0, gx, gy, gz]; LUNEBURG [., cx, cy, cz, 1/R^2];
-// FIBER [n_c, Delta, ., cx, cy, 2 Delta n_c^2/R^2, n_clad, R^2];
-// GAUSSIAN [n0, largest dL0 for the degree-3 difference form]; others [n0]
+// MedF.q: HOMOGENEOUS [n, n - (float)n]; LINEAR [n0, gx, gy, gz, n0 - (float)n0];
+// LUNEBURG [., cx, cy, cz, 1/R^2]; FIBER [n_c, Delta, ., cx, cy, 2 Delta n_c^2/R^2,
+// n_clad, R^2]; GAUSSIAN [n0, largest dL0 for the degree-3 difference form,
+// n0 - (float)n0]; others [n0]
 template <int MK, class BumpPtr>
 __device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf, BumpPtr bumps, float dL0,
-                                      f3 P, f3 s, float n_last, float &n, f3 &g, float &dn) {
+                                      f3 P, f3 s, float n_last, float &n, float &nl, f3 &g,
+                                      float &dn) {
     static_assert(!kIndexIn64<MK>, "index taken in double by the march");
+    nl = 0.0f;
     if constexpr (MK == VRT_MEDIUM_HOMOGENEOUS) {
         n = mf.q[0];
+        nl = mf.q[1];
         g = mkf(0, 0, 0);
         dn = 0.0f;
     } else if constexpr (MK == VRT_MEDIUM_LINEAR) {
         g = mkf(mf.q[1], mf.q[2], mf.q[3]);
-        n = mf.q[0] + dotf(g, P);
+        const float v = dotf(g, P);
+        n = mf.q[0] + v;
+        nl = ((mf.q[0] - n) + v) + mf.q[4];
         dn = dotf(g, s);
     } else if constexpr (MK == VRT_MEDIUM_LUNEBURG) {
         // n^2 = 2 - u, u = |P-C|^2/R^2:  n_i - n_{i-1} = -(u_i - u_{i-1}) / (n_i + n_{i-1}),
@@ -367,7 +376,7 @@ __device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf, BumpPt
         // E_k(P_{i-1}) = E_k(P_i) exp(dq_k), dq_k = ((P_i - c_k).s - |s|^2/2) / sigma^2,
         // so n_i - n_{i-1} = -sum A_k E_k(P_i) expm1(dq_k), with A_k expm1 as a
         // polynomial in y = sigma^2 dq_k whose coefficients carry A_k.
-        float nn = mf.q[0], gx = 0.f, gy = 0.f, gz = 0.f, acc = 0.f;
+        float nn = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, acc = 0.f;
         const float hs2 = -0.5f * dotf(s, s);
         const BumpPtr b = bumps;
         const int K = m.K;
@@ -397,7 +406,8 @@ __device__ __forceinline__ void med32(const MediumDev &m, const MedF &mf, BumpPt
             bump_loop(std::integral_constant<int, 3>{});
         else
             bump_loop(std::integral_constant<int, 5>{});
-        n = nn;
+        n = mf.q[0] + nn;
+        nl = ((mf.q[0] - n) + nn) + mf.q[2];
         g = mkf(gx, gy, gz);
         dn = acc;
     }

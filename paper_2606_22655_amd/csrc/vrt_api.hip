@@ -46,18 +46,70 @@ bool vrt::gpu_accessible(const void *p) {
     return a.type != hipMemoryTypeUnregistered;
 }
 
+// Medium memory comes from the stream-ordered allocator on the context's
+// library stream, so that a medium can be freed in stream order behind the
+// launches that read it, without blocking the host (a plain hipFree waits for
+// the device, which may hold a resident serving kernel).
 static int dev_alloc(vrt_medium_t m, void **p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) return fail_hip(e, "hipMalloc (medium)");
+    hipError_t e = m->async_allocs ? hipMallocAsync(p, bytes, m->ctx->aux) : hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail_hip(e, "device allocation (medium)");
     m->allocs.push_back(*p);
     m->bytes += bytes;
     return VRT_OK;
 }
 
+// Wait for the medium's uploads on the library stream.
+static hipError_t medium_ready(vrt_medium_t m) { return hipStreamSynchronize(m->ctx->aux); }
+
+// Free a medium after every eager launch recorded on it: the library stream
+// waits for their events, then returns the memory in stream order.  The host
+// does not wait.  (Without the stream-ordered allocator: wait, then free.)
 static void free_medium(vrt_medium_t m) {
-    for (void *p : m->allocs) (void)hipFree(p);
+    vrt_context_t ctx = m->ctx;
+    {
+        std::lock_guard<std::mutex> lk(m->use_mu);
+        for (const MediumUse &u : m->uses) {
+            if (m->async_allocs)
+                (void)hipStreamWaitEvent(ctx->aux, u.ev, 0);
+            else
+                (void)hipEventSynchronize(u.ev);
+            (void)hipEventDestroy(u.ev);
+        }
+        m->uses.clear();
+    }
+    for (void *p : m->allocs) (void)(m->async_allocs ? hipFreeAsync(p, ctx->aux) : hipFree(p));
     m->allocs.clear();
     delete m;
+}
+
+// Record that a launch on `stream` reads the medium (one event per stream:
+// recording again on the same stream supersedes the earlier launch, which
+// completes first).  A launch captured in a graph is not recorded: the caller
+// who owns the graph keeps the medium alive while the graph may replay.
+static int note_use(vrt_medium_t m, hipStream_t stream, bool captured) {
+    if (captured) return VRT_OK;
+    std::lock_guard<std::mutex> lk(m->use_mu);
+    for (MediumUse &u : m->uses)
+        if (u.stream == stream) {
+            HIP_TRY(hipEventRecord(u.ev, stream), "hipEventRecord (medium use)");
+            return VRT_OK;
+        }
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate (medium use)");
+    hipError_t e = hipEventRecord(ev, stream);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        return fail_hip(e, "hipEventRecord (medium use)");
+    }
+    m->uses.push_back(MediumUse{stream, ev});
+    return VRT_OK;
+}
+
+static int stream_captured(hipStream_t stream, bool &captured) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &cs), "hipStreamIsCapturing");
+    captured = cs != hipStreamCaptureStatusNone;
+    return VRT_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -166,10 +218,24 @@ int vrt_context_create(int hip_device, vrt_context_t *out) {
     hipError_t e = hipMalloc((void **)&c->queues, sizeof(uint32_t) * kQueueSlots * kQueueStride);
     if (e == hipSuccess)
         e = hipMalloc((void **)&c->counters, sizeof(unsigned long long) * kNumCounters);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    for (int i = 0; i < kEagerSlots && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&c->slot_ev[i], hipEventDisableTiming);
+    if (e == hipSuccess) {
+        int pools = 0;
+        if (hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, hip_device) !=
+                hipSuccess)
+            pools = 0;
+        c->async_pools = pools != 0;
+    }
     if (e != hipSuccess) {
+        for (int i = 0; i < kEagerSlots; ++i)
+            if (c->slot_ev[i]) (void)hipEventDestroy(c->slot_ev[i]);
+        if (c->aux) (void)hipStreamDestroy(c->aux);
+        if (c->counters) (void)hipFree(c->counters);
         if (c->queues) (void)hipFree(c->queues);
         delete c;
-        return fail_hip(e, "vrt_context_create: hipMalloc");
+        return fail_hip(e, "vrt_context_create");
     }
     *out = c;
     return VRT_OK;
@@ -183,7 +249,10 @@ int vrt_context_destroy(vrt_context_t ctx) {
         return fail(VRT_EINVAL, "vrt_context_destroy: %d servers still alive",
                     ctx->n_servers.load());
     (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->aux);  // deferred medium frees
     (void)hipDeviceSynchronize();
+    for (int i = 0; i < kEagerSlots; ++i) (void)hipEventDestroy(ctx->slot_ev[i]);
+    (void)hipStreamDestroy(ctx->aux);
     (void)hipFree(ctx->queues);
     (void)hipFree(ctx->counters);
     delete ctx;
@@ -242,6 +311,7 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
     if (rc) return rc;
     auto *m = new vrt_medium_s();
     m->ctx = ctx;
+    m->async_allocs = ctx->async_pools;
     m->bnd = b;
     MediumDev &d = m->dev;
     d.kind = kind;
@@ -256,12 +326,14 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
         }
         d.q[0] = p[0];
         f.q[0] = (float)p[0];
+        f.q[1] = (float)(p[0] - (double)f.q[0]);  // low part of the step's index
         break;
     case VRT_MEDIUM_LINEAR:
         for (int i = 0; i < 4; ++i) {
             d.q[i] = p[i];
             f.q[i] = (float)p[i];
         }
+        f.q[4] = (float)(p[0] - (double)f.q[0]);
         break;
     case VRT_MEDIUM_LUNEBURG:
         if (!(p[0] > 0.0)) {
@@ -340,7 +412,9 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
             free_medium(m);
             return rc;
         }
-        hipError_t e = hipMemcpy(pd, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+        hipError_t e = hipMemcpyAsync(pd, tab.data(), tab.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, ctx->aux);
+        if (e == hipSuccess) e = medium_ready(m);
         if (e != hipSuccess) {
             free_medium(m);
             return fail_hip(e, "hipMemcpy (zernike coefficients)");
@@ -383,6 +457,7 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
         // step bounds of the single-precision index difference (media.h)
         const double nmin_sig = (p[0] - amp) * sig_min;
         f.q[1] = (float)(kGaussRho3 * nmin_sig);
+        f.q[2] = (float)(p[0] - (double)f.q[0]);
         m->fp32_max_dL0 = kGaussRhoMax * nmin_sig;
         void *pd = nullptr, *pf = nullptr;
         if ((rc = dev_alloc(m, &pd, bd.size() * sizeof(double))) ||
@@ -390,9 +465,12 @@ int vrt_medium_create_analytic(vrt_context_t ctx, int kind, const double *params
             free_medium(m);
             return rc;
         }
-        hipError_t e = hipMemcpy(pd, bd.data(), bd.size() * sizeof(double), hipMemcpyHostToDevice);
+        hipError_t e = hipMemcpyAsync(pd, bd.data(), bd.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, ctx->aux);
         if (e == hipSuccess)
-            e = hipMemcpy(pf, bf.data(), bf.size() * sizeof(float), hipMemcpyHostToDevice);
+            e = hipMemcpyAsync(pf, bf.data(), bf.size() * sizeof(float), hipMemcpyHostToDevice,
+                               ctx->aux);
+        if (e == hipSuccess) e = medium_ready(m);
         if (e != hipSuccess) {
             free_medium(m);
             return fail_hip(e, "hipMemcpy (gaussian params)");
@@ -426,6 +504,7 @@ int vrt_medium_create_grid(vrt_context_t ctx, const float *values, int nx, int n
     if (rc) return rc;
     auto *m = new vrt_medium_s();
     m->ctx = ctx;
+    m->async_allocs = ctx->async_pools;
     m->bnd.kind = VRT_BOUNDARY_BOX;
     for (int a = 0; a < 3; ++a) {
         m->bnd.p[a] = lo[a];
@@ -455,23 +534,30 @@ int vrt_medium_create_grid(vrt_context_t ctx, const float *values, int nx, int n
         free_medium(m);
         return rc;
     }
-    hipError_t e = hipMemcpy(g, values, total * sizeof(float),
-                             values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&bad, sizeof(unsigned int));
-    if (e == hipSuccess) e = hipMemset(bad, 0, sizeof(unsigned int));
+    // uploads and the record kernel run on the library stream (a device-side
+    // `values` array must be complete when this is called)
+    hipStream_t st = ctx->aux;
+    hipError_t e = hipMemcpyAsync(g, values, total * sizeof(float),
+                                  values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                  st);
+    if (e == hipSuccess)
+        e = m->async_allocs ? hipMallocAsync(&bad, sizeof(unsigned int), st)
+                            : hipMalloc(&bad, sizeof(unsigned int));
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(unsigned int), st);
     if (e != hipSuccess) {
-        if (bad) (void)hipFree(bad);
+        if (bad) (void)(m->async_allocs ? hipFreeAsync(bad, st) : hipFree(bad));
         free_medium(m);
         return fail_hip(e, "vrt_medium_create_grid: copy");
     }
     size_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(grid_records_kernel, dim3((unsigned)blocks), dim3(256), 0, 0,
+    hipLaunchKernelGGL(grid_records_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
                        (const float *)g, (float4 *)r, nx, ny, nz, (unsigned int *)bad);
     unsigned int hbad = 0;
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpy(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost);
-    (void)hipFree(bad);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = medium_ready(m);
+    (void)(m->async_allocs ? hipFreeAsync(bad, st) : hipFree(bad));
     if (e != hipSuccess) {
         free_medium(m);
         return fail_hip(e, "vrt_medium_create_grid: records");
@@ -494,11 +580,10 @@ int vrt_medium_destroy(vrt_medium_t m) {
         return fail(VRT_EINVAL, "vrt_medium_destroy: %d server jobs on it are not done",
                     m->jobs.load());
     vrt_context_t ctx = m->ctx;
-    (void)hipSetDevice(ctx->device);
-    hipError_t e = hipDeviceSynchronize();
-    free_medium(m);
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    free_medium(m);  // deferred behind the launches that read it; the host does not wait
     ctx->n_media--;
-    if (e != hipSuccess) return fail_hip(e, "vrt_medium_destroy: device synchronize");
     return VRT_OK;
 }
 
@@ -586,6 +671,8 @@ int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, s
     vrt_context_t ctx = m->ctx;
     int rc = set_device(ctx);
     if (rc) return rc;
+    bool captured = false;
+    if ((rc = stream_captured((hipStream_t)stream, captured))) return rc;
     LaunchArgs a{};
     fill_launch(m, p, n_rays, stream, a);
     hipError_t e;
@@ -599,12 +686,29 @@ int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, s
                                 (float *)rays->ox, (float *)rays->oy, (float *)rays->oz,
                                 (float *)rays->odx, (float *)rays->ody, (float *)rays->odz,
                                 rays->status, rays->steps, rays->n_tir, rays->n_btir, rays->flags};
-        const uint32_t slot = ctx->next_slot.fetch_add(1) % kQueueSlots;
+        std::lock_guard<std::mutex> lk(ctx->slot_mu);
+        uint32_t slot;
+        if (captured) {
+            if (ctx->n_captured >= (uint32_t)(kQueueSlots - kEagerSlots))
+                return fail(VRT_ENOMEM, "vrt_trace: %d single-precision traces captured in graphs "
+                                        "on this context already (each keeps its queue slot)",
+                            kQueueSlots - kEagerSlots);
+            slot = kEagerSlots + ctx->n_captured++;
+        } else {
+            slot = ctx->next_eager++ % kEagerSlots;
+            if (ctx->slot_recorded[slot])  // the slot's previous launch ends first
+                HIP_TRY(hipStreamWaitEvent((hipStream_t)stream, ctx->slot_ev[slot], 0),
+                        "vrt_trace: hipStreamWaitEvent");
+        }
         a.queue = ctx->queues + (size_t)slot * kQueueStride;
         e = launch_march_fp32c(a);
+        if (e == hipSuccess && !captured) {
+            e = hipEventRecord(ctx->slot_ev[slot], (hipStream_t)stream);
+            if (e == hipSuccess) ctx->slot_recorded[slot] = true;
+        }
     }
     if (e != hipSuccess) return fail_hip(e, "vrt_trace: launch");
-    return VRT_OK;
+    return note_use(m, (hipStream_t)stream, captured);
 }
 
 int vrt_trace_paths(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays,
@@ -622,12 +726,14 @@ int vrt_trace_paths(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *r
         return fail(VRT_EINVAL, "vrt_trace_paths: path or n_points is pageable host memory");
     int rc = set_device(m->ctx);
     if (rc) return rc;
+    bool captured = false;
+    if ((rc = stream_captured((hipStream_t)stream, captured))) return rc;
     LaunchArgs a{};
     fill_launch(m, p, n_rays, stream, a);
     a.io64 = rays64(rays);
     hipError_t e = launch_paths_fp64(a, path, cap, n_points);
     if (e != hipSuccess) return fail_hip(e, "vrt_trace_paths: launch");
-    return VRT_OK;
+    return note_use(m, (hipStream_t)stream, captured);
 }
 
 int vrt_reduce_counters(vrt_context_t ctx, const vrt_rays *rays, size_t n_rays, vrt_counters *out,
@@ -637,6 +743,13 @@ int vrt_reduce_counters(vrt_context_t ctx, const vrt_rays *rays, size_t n_rays, 
                        !aligned(rays->n_tir, 4) || !aligned(rays->n_btir, 4) ||
                        !aligned(rays->flags, 4)))
         return fail(VRT_EINVAL, "vrt_reduce_counters: result array NULL or misaligned");
+    if (n_rays > 0) {
+        const void *uptrs[] = {rays->status, rays->steps, rays->n_tir, rays->n_btir, rays->flags};
+        for (const void *q : uptrs)
+            if (!gpu_accessible(q))
+                return fail(VRT_EINVAL, "vrt_reduce_counters: a result array is pageable host "
+                                        "memory (not GPU-accessible)");
+    }
     int rc = set_device(ctx);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(ctx->counters_mu);

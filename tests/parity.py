@@ -1,20 +1,25 @@
 """Element-by-element comparison of GPU results with the FP64 oracle.
 
-Bar (per ray, on the same seeded inputs):
+The bar, per ray, on the same seeded inputs (the pass rule):
   - status, interior TIR count and surface TIR count identical;
-  - exit position within pos_tol * aperture, exit direction within dir_tol rad;
-except rays the oracle flags as near-critical (some refraction/TIR decision
-within crit_rad of the critical angle), near-grazing (a refraction into higher
-index within crit_rad of tangency, where the sign of N.I in Eq. (10) decides
-the side) or near-tie (some step ended within tie_eps of the enclosing
-surface, so that "full step or cut" is decided by the last bits): those are
-exempt, and each kind is counted.  Step counts are reported.
+  - exit position within pos_tol * aperture;
+  - exit direction, as it leaves the medium, within dir_tol rad;
+except
+  - rays the oracle flags near-critical: some refraction/TIR decision within
+    crit_rad (1e-6 rad) of the critical angle (counted, exempt);
+  - rays the oracle flags near-grazing: a refraction into higher index with
+    |N.I| < crit_rad, where the sgn(N.I) of Eq. (10) alone decides on which
+    side of the isoindicial surface the ray continues (counted, exempt; the
+    window is pinned on the oracle).
+Nothing else is set aside: near-tie rays (a step of the oracle ended within
+tie_eps of the enclosing surface, so "full step or cut" was decided by the
+last bits) meet every check; only their step count may differ.  Step counts
+are reported, not part of the bar.
 
-The oracle also marks each of those windows ten times wider.  A ray with a
-decision inside a wide window may still differ -- the single-precision march
-reaches such a decision with its state off by up to a few 1e-6 rad after TIR
-events -- so a wide-window ray that fails the bar is set aside and counted
-as a "soft flip" (assert_parity bounds their number) instead of failing.
+Diagnostics, reported beside the pass/fail counts: the exit direction error
+measured inside the medium (the final refraction's gain n_in cos t_in /
+(n_amb cos t_out), Snell's law differentiated, divided out), and how many of
+the failing rays the oracle marks in its ten times wider windows.
 """
 from __future__ import annotations
 
@@ -95,70 +100,80 @@ def exit_gain(spec, orc, n_index):
 
 
 def compare(orc, gpu, aperture, pos_tol=1e-4, dir_tol=1e-4, spec=None):
-    """spec (the medium) given: the exit direction's bar is dir_tol times the
-    exit refraction's gain (exit_gain), i.e. dir_tol on the direction inside."""
+    """Per-ray comparison under the pass rule of this module.  spec (the
+    medium) given: also the inside-the-medium direction error (diagnostic)."""
     n = len(orc["status"])
-    dir_gain = None
+    gain = np.ones(n)
     if spec is not None:
         import oracle
 
-        dir_gain = exit_gain(spec, orc, lambda P: oracle.evaluate(spec, P)[0])
-    ex_o = (orc["flags"] & EXEMPT) != 0
-    ex_g = (gpu["flags"] & EXEMPT) != 0
-    keep = ~ex_o
+        gain = np.asarray(exit_gain(spec, orc, lambda P: oracle.evaluate(spec, P)[0]))
+    fo, fg = orc["flags"], gpu["flags"]
+    crit = (fo & F_NEAR_CRITICAL) != 0
+    graze = (fo & F_NEAR_GRAZING) != 0
+    tie = (fo & F_NEAR_TIE) != 0
+    dsteps = orc["steps"].astype(np.int64) - gpu["steps"].astype(np.int64)
+    checked = ~crit & ~graze
     st = orc["status"] == gpu["status"]
     tir = orc["ntir"] == gpu["ntir"]
     btir = orc["nbtir"] == gpu["nbtir"]
     pe = np.linalg.norm(orc["P"] - gpu["P"], axis=1)
     de = angle_between(orc["D"], gpu["D"])
-    dtol = dir_tol * (np.ones(n) if dir_gain is None else np.asarray(dir_gain))
-    fails = ~st | ~tir | ~btir | (pe > pos_tol * aperture) | (de > dtol)
-    soft = keep & ((orc["flags"] & WIDE) != 0) & fails
-    keep = keep & ~soft
-    same = keep & st
+    de_in = de / gain
+    same = checked & st
     bad_pos = same & (pe > pos_tol * aperture)
-    bad_dir = same & (de > dtol)
-    dsteps = orc["steps"].astype(np.int64) - gpu["steps"].astype(np.int64)
+    bad_dir = same & (de > dir_tol)
+    fail = checked & (~st | ~tir | ~btir | bad_pos | bad_dir)
+    wide = (fo & WIDE) != 0
+
+    def mx(v, m):
+        return float(v[m].max()) if m.any() else 0.0
+
+    def pct(v, m, q):
+        return float(np.percentile(v[m], q)) if m.any() else 0.0
+
     rep = {
         "n": n,
-        "flagged_oracle": int(ex_o.sum()),
-        "flagged_oracle_critical": int(((orc["flags"] & F_NEAR_CRITICAL) != 0).sum()),
-        "flagged_oracle_tie": int(((orc["flags"] & F_NEAR_TIE) != 0).sum()),
-        "flagged_oracle_grazing": int(((orc["flags"] & F_NEAR_GRAZING) != 0).sum()),
-        "flagged_gpu": int(ex_g.sum()),
-        "flagged_union": int((ex_o | ex_g).sum()),
-        "soft_flips": int(soft.sum()),
-        "status_mismatch": int((keep & ~st).sum()),
-        "tir_mismatch": int((keep & ~tir).sum()),
-        "btir_mismatch": int((keep & ~btir).sum()),
+        "checked": int(checked.sum()),
+        "fail": int(fail.sum()),
+        "exempt_critical": int(crit.sum()),
+        "exempt_grazing": int((graze & ~crit).sum()),
+        "tie_checked": int((tie & checked).sum()),
+        "tie_steps_differ": int((tie & checked & (dsteps != 0)).sum()),
+        "flagged_oracle_critical": int(crit.sum()),
+        "flagged_oracle_tie": int(tie.sum()),
+        "flagged_oracle_grazing": int(graze.sum()),
+        "flagged_gpu_critical": int(((fg & F_NEAR_CRITICAL) != 0).sum()),
+        "flagged_gpu_tie": int(((fg & F_NEAR_TIE) != 0).sum()),
+        "flagged_gpu_grazing": int(((fg & F_NEAR_GRAZING) != 0).sum()),
+        "status_mismatch": int((checked & ~st).sum()),
+        "tir_mismatch": int((checked & ~tir).sum()),
+        "btir_mismatch": int((checked & ~btir).sum()),
         "pos_fail": int(bad_pos.sum()),
         "dir_fail": int(bad_dir.sum()),
-        "steps_mismatch": int((keep & (dsteps != 0)).sum()),
-        "steps_absmax": int(np.abs(dsteps[keep]).max()) if keep.any() else 0,
-        "pos_err_max": float(pe[same].max()) if same.any() else 0.0,
-        "pos_err_p99": float(np.percentile(pe[same], 99)) if same.any() else 0.0,
-        "pos_err_p50": float(np.percentile(pe[same], 50)) if same.any() else 0.0,
-        "dir_err_max": float(de[same].max()) if same.any() else 0.0,
-        "dir_err_p99": float(np.percentile(de[same], 99)) if same.any() else 0.0,
-        "dir_err_inside_max": float((de / (dtol / dir_tol))[same].max()) if same.any() else 0.0,
-        "exempt_pos_err_max": float(pe[ex_o].max()) if ex_o.any() else 0.0,
+        "fail_in_wide_window": int((fail & wide).sum()),
+        "steps_mismatch": int((checked & (dsteps != 0)).sum()),
+        "steps_absmax": int(np.abs(dsteps[checked]).max()) if checked.any() else 0,
+        "pos_err_max": mx(pe, same),
+        "pos_err_p99": pct(pe, same, 99),
+        "pos_err_p50": pct(pe, same, 50),
+        "dir_err_max": mx(de, same),
+        "dir_err_p99": pct(de, same, 99),
+        "dir_err_inside_max": mx(de_in, same),
+        "exempt_pos_err_max": mx(pe, ~checked),
         "tir_total_oracle": int(orc["ntir"].sum()),
         "btir_total_oracle": int(orc["nbtir"].sum()),
     }
-    rep["bad_rays"] = np.nonzero(keep & (~st | ~tir | ~btir | bad_pos | bad_dir))[0][:20].tolist()
+    rep["bad_rays"] = np.nonzero(fail)[0][:20].tolist()
     return rep
 
 
-def assert_parity(rep, max_steps_mismatch_frac=1e-3, max_steps_delta=2, max_soft_frac=1e-3):
+def assert_parity(rep):
+    """The pass rule: no checked ray fails."""
     msg = {k: v for k, v in rep.items()}
-    assert rep["soft_flips"] <= max(1, max_soft_frac * rep["n"]), msg
-    assert rep["status_mismatch"] == 0, msg
-    assert rep["tir_mismatch"] == 0, msg
-    assert rep["btir_mismatch"] == 0, msg
-    assert rep["pos_fail"] == 0, msg
-    assert rep["dir_fail"] == 0, msg
-    assert rep["steps_mismatch"] <= max(1, max_steps_mismatch_frac * rep["n"]), msg
-    assert rep["steps_absmax"] <= max_steps_delta, msg
+    assert rep["fail"] == 0, msg
+    assert rep["status_mismatch"] == 0 and rep["tir_mismatch"] == 0, msg
+    assert rep["btir_mismatch"] == 0 and rep["pos_fail"] == 0 and rep["dir_fail"] == 0, msg
 
 
 def stat_compare(orc, gpu, n_bins=8, face_axis=2):

@@ -406,6 +406,9 @@ def test_pageable_host_arrays_are_refused(vrt, ctx):
         stream = torch.cuda.current_stream().cuda_stream
         with pytest.raises(vrt.VrtError, match="pageable"):
             vrt.vrt_trace(med.handle, vrt.make_params(prm, "fp32c"), r, 64, stream)
+        # the counter reduction reads the five result arrays: refused before its launch
+        with pytest.raises(vrt.VrtError, match="pageable"):
+            vrt.vrt_reduce_counters(ctx.handle, r, 64, stream)
         # one device array swapped in is not enough
         b = vrt.RayBatch(P0, d0, "fp32c")
         b.rays.oz = host[8].ctypes.data_as(C.c_void_p).value

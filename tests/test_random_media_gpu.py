@@ -121,7 +121,7 @@ def test_random_medium_parity(vrt, ctx, orc, seed):
             print(f"\n[random {seed} {spec['kind']} in {spec['boundary']['kind']} {precision}] "
                   f"status {np.bincount(o['status'], minlength=6).tolist()} "
                   f"TIR {int(o['ntir'].sum())} bTIR {int(o['nbtir'].sum())} "
-                  f"pos_err_max {rep['pos_err_max']:.2e} soft {rep['soft_flips']}", flush=True)
+                  f"pos_err_max {rep['pos_err_max']:.2e} fail {rep['fail']}", flush=True)
             assert_parity(rep)
     finally:
         med.close()

@@ -90,3 +90,91 @@ def test_trace_captured_in_a_graph_replays_the_eager_result(vrt, ctx):
         del g
     finally:
         med.close()
+
+
+def test_graph_replays_beside_more_than_1024_eager_traces(vrt, ctx):
+    """A single-precision trace captured in a graph keeps a ray-queue counter
+    of its own: replayed while 1,100 eager traces (more than the context's
+    1,024 counters) run on another stream, every replay still equals the eager
+    result bitwise, and so do the eager traces."""
+    import torch
+
+    spec, rays, prm = workloads.gaussian_cube(n_rays=16384)
+    eager_rays = workloads.face_cone_rays(2048, 517, 20.0)
+    prm_short = dict(prm, max_steps=400)
+    med = vrt.Medium(ctx, spec)
+    try:
+        a = vrt.RayBatch(rays[0], rays[1], "fp32c")
+        vrt.trace(med, a, prm, "fp32c")
+        bref = vrt.RayBatch(eager_rays[0], eager_rays[1], "fp32c")
+        vrt.trace(med, bref, prm_short, "fp32c")
+        torch.cuda.synchronize()
+        want_a, want_b = a.results(), bref.results()
+        g = torch.cuda.CUDAGraph()
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()  # default priority
+        s1.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s1):
+            with torch.cuda.graph(g, stream=s1):
+                vrt.trace(med, a, prm, "fp32c", stream=torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        outs = [vrt.RayBatch(eager_rays[0], eager_rays[1], "fp32c") for _ in range(4)]
+        torch.cuda.synchronize()
+        n_eager, replays = 1100, 0
+        for k in range(n_eager):
+            vrt.trace(med, outs[k % 4], prm_short, "fp32c", stream=s2.cuda_stream)
+            if k % 100 == 50:
+                a.out.fill_(float("nan"))
+                a.u32.fill_(-1)
+                torch.cuda.synchronize()
+                with torch.cuda.stream(s1):
+                    g.replay()
+                replays += 1
+                s1.synchronize()
+                assert same(want_a, a.results()), k
+        torch.cuda.synchronize()
+        assert replays == 11
+        for b in outs:
+            assert same(want_b, b.results())
+        del g
+    finally:
+        med.close()
+
+
+def test_medium_destroy_defers_the_free_behind_a_running_trace(vrt, ctx):
+    """vrt_medium_destroy returns without waiting for a trace still running on
+    the medium; the memory is freed behind it, so the trace's results are
+    intact, and a medium created right after works."""
+    import time
+
+    import torch
+
+    spec, rays, prm = workloads.gaussian_cube(n_rays=1 << 19)
+    med = vrt.Medium(ctx, spec)
+    b = vrt.RayBatch(rays[0], rays[1], "fp32c")
+    vrt.trace(med, b, prm, "fp32c")
+    torch.cuda.synchronize()
+    want = b.results()
+    s = torch.cuda.Stream()
+    b2 = vrt.RayBatch(rays[0], rays[1], "fp32c")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vrt.trace(med, b2, prm, "fp32c", stream=s.cuda_stream)
+    t1 = time.perf_counter()
+    med.close()  # the trace is still running
+    t2 = time.perf_counter()
+    s.synchronize()
+    t3 = time.perf_counter()
+    print(f"\n[destroy] launch {1e3 * (t1 - t0):.3f} ms, destroy {1e3 * (t2 - t1):.3f} ms, "
+          f"trace done after {1e3 * (t3 - t0):.1f} ms", flush=True)
+    assert (t3 - t0) > 0.01 and (t2 - t1) < 0.25 * (t3 - t0)
+    assert same(want, b2.results())
+    # a new medium (its memory may be the freed one) traces correctly
+    med2 = vrt.Medium(ctx, spec)
+    try:
+        b3 = vrt.RayBatch(rays[0][:4096], rays[1][:4096], "fp32c")
+        vrt.trace(med2, b3, prm, "fp32c")
+        torch.cuda.synchronize()
+        got = b3.results()
+        assert all(np.array_equal(got[k], want[k][:4096]) for k in KEYS)
+    finally:
+        med2.close()
