@@ -276,6 +276,27 @@ int vrt_n2p_sweep(vrt_medium_t lens, const double *beta_gamma, size_t n_cand, co
                   size_t n_rays, double z_launch, const vrt_trace_params *p, double *rmse,
                   double *z_int, uint64_t *steps, void *stream);
 
+/* vrt_n2p_sweep for callers that cannot allocate device memory (code that
+ * must not call hipMalloc / hipFree, tight design loops that call the sweep
+ * once per refinement level).  Same arguments, results and errors as
+ * vrt_n2p_sweep; the sweep's device buffers (candidate descriptors, ray
+ * heights, RMSE, and z_int / steps when asked for) are carved from one fixed
+ * 4 MiB device array that the library holds on each device it runs on until
+ * the process ends, instead of being allocated per call.  It calls no
+ * hipMalloc, hipFree or allocating library routine.
+ *   Limit: the buffers, each rounded up to 256 bytes -- 264 * n_cand
+ *   (descriptors) + 8 * n_rays + 8 * n_cand (RMSE), plus 8 * n_cand * n_rays
+ *   with z_int and 8 * n_cand with steps -- must fit in 4 MiB (about 14,900
+ *   candidates of 10 rays, 11,600 with z_int and steps); beyond that the
+ *   call returns EINVAL without touching the device.
+ *   Every call on a device shares that device's array: calls that overlap in
+ *   time on one device (from several threads or streams) race and must not
+ *   be issued.  Each call synchronises `stream` before returning. */
+int vrt_n2p_sweep_noalloc(vrt_medium_t lens, const double *beta_gamma, size_t n_cand,
+                          const double *y, size_t n_rays, double z_launch,
+                          const vrt_trace_params *p, double *rmse, double *z_int,
+                          uint64_t *steps, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Gradient of an exit-plane loss with respect to a grid medium's node values
  * (the direct-design use of the march, Sec. VI, made differentiable).

@@ -35,7 +35,7 @@ EXPORTED = ["vrt_abi_version", "vrt_context_create", "vrt_context_destroy",
             "vrt_medium_device_bytes", "vrt_trace", "vrt_reduce_counters", "vrt_last_error",
             "vrt_server_create", "vrt_server_submit", "vrt_server_query", "vrt_server_wait",
             "vrt_server_stats_get", "vrt_server_destroy", "vrt_n2p_sweep", "vrt_grid_loss_grad",
-            "vrt_trace_paths"]
+            "vrt_trace_paths", "vrt_n2p_sweep_noalloc"]
 JOB_STATES = {0: "QUEUED", 1: "RUNNING", 2: "COPYING", 3: "DONE"}
 
 
@@ -135,6 +135,7 @@ def load_library(path=LIB_PATH):
     lib.vrt_n2p_sweep.argtypes = [vp, dp, C.c_size_t, dp, C.c_size_t, C.c_double,
                                   C.POINTER(vrt_trace_params), dp, dp,
                                   C.POINTER(C.c_uint64), vp]
+    lib.vrt_n2p_sweep_noalloc.argtypes = lib.vrt_n2p_sweep.argtypes
     lib.vrt_last_error.restype = C.c_char_p
     lib.vrt_last_error.argtypes = []
     for name in EXPORTED:
@@ -217,6 +218,14 @@ def vrt_n2p_sweep(lens, beta_gamma, y, z_launch, params, stream=0, want_z=False,
     crossings (n_cand, n_rays) and the ray-steps per candidate."""
     return _sweep(load_library().vrt_n2p_sweep, lens, beta_gamma, y, z_launch, params, stream,
                   want_z, want_steps)
+
+
+def vrt_n2p_sweep_noalloc(lens, beta_gamma, y, z_launch, params, stream=0, want_z=False,
+                          want_steps=False):
+    """vrt_n2p_sweep with the device buffers in the library's fixed scratch
+    array (no device allocation per call)."""
+    return _sweep(load_library().vrt_n2p_sweep_noalloc, lens, beta_gamma, y, z_launch, params,
+                  stream, want_z, want_steps)
 
 
 def _sweep(fn, lens, beta_gamma, y, z_launch, params, stream, want_z, want_steps):
