@@ -9,15 +9,22 @@ A "step" of this benchmark is one pass of the whole hot path over one batch:
 one vrt_trace call that launches, enters, marches (medium evaluation, normal,
 Snell/TIR/tangential/straight dispatch, compensated constant-OPL move,
 surface refraction or reflection) and retires every ray of the batch, with the
-inputs already resident in HBM.  The default workload is the freeform
-analytic configuration: unit cube in air, n = 1.5 + 16 seeded Gaussian bumps,
-1,048,576 rays from z = 0 in a 20 deg cone, dL0 = 5e-4, FP32 with
-compensated sums and an FP64 discriminant.
+inputs already resident in HBM.
 
-Prints one JSON line: ray-steps/s (value), the roofline of the march kernel
-(algorithmic work / measured kernel time vs the chip's peak), the FP64 CPU
-oracle's rate on a bounded sample of the same rays (cpu_baseline), and the
-parity of the timed GPU results against that oracle sample.
+The default (headline) workload is the largest single-GPU configuration: the
+discretized isoindicial medium, a 256^3 FP32 index grid of smoothed noise
+quantized to 32 levels in [1.4, 1.8], 4,194,304 rays from z = 0 in a 30 deg
+cone, dL0 = 5e-4, FP32 with compensated sums.  Its record carries the roofline
+of the march kernel (algorithmic bytes of the visited cells against HBM, the
+VALU side beside it), the FP64 oracle's rate on a bounded sample of the same
+rays (cpu_baseline) and the parity of the timed results.  Two sub-records
+follow: "freeform" (the 16-Gaussian-bump cube, 1,048,576 rays, 20 deg cone,
+with per-ray parity of 524,288 rays against the oracle) and "served" (a
+Poisson stream of 120 jobs at 80 % of the measured capacity over eight
+resident media, its rays/s and p50/p99 latency next to one plain FP64 launch
+per job, and the parity of sampled served rays).
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -199,12 +206,9 @@ def cpu_baseline(spec, rays, prm, sample, g_res, aperture):
     sub = {k: v[:n] for k, v in g_res.items()}
     if spec["kind"] == "grid":
         # single rays through the quantized grid are chaotic (the oracle's own
-        # exits move under 1e-11 launch shifts): compare distributions
-        from parity import stat_compare
-
-        rep = stat_compare(r, sub)
-        rep["kind"] = "two-sample statistics (chaotic medium)"
-        return base, rep
+        # exits move under 1e-11 launch shifts): the caller compares the
+        # distributions of these full paths and single rays over 128 moves
+        return base, None, (r, np.arange(n))
     chaotic = spec["kind"] in ("spherical", "zernike")
     if chaotic:
         # rays trapped by repeated TIR (in the sphere, along the lens wall)
@@ -225,7 +229,7 @@ def cpu_baseline(spec, rays, prm, sample, g_res, aperture):
             "btir_mismatch", "pos_fail", "dir_fail", "fail_in_wide_window", "steps_mismatch",
             "steps_absmax", "pos_err_max", "pos_err_p99", "dir_err_max", "dir_err_p99",
             "dir_err_inside_max", "ill_conditioned", "bad_rays")
-    return base, {k: rep[k] for k in keys if k in rep}
+    return base, {k: rep[k] for k in keys if k in rep}, None
 
 
 # ---------------------------------------------------------------------------
@@ -261,6 +265,59 @@ def job_buffers(vrt, torch, pool, off, n):
     for i, k in enumerate(("status", "steps", "n_tir", "n_btir", "flags")):
         setattr(r, k, u32[i].data_ptr())
     return r, (out, u32)
+
+
+def served_parity(vrt, torch, jobs, keep, pools, meds, media, prm, offset, n_jobs=16,
+                  n_oracle=256):
+    """Parity of the served results: for a seeded sample of jobs, every ray of
+    the job against a vrt_trace batch launch of the same rays (bitwise: the
+    served kernel runs the batch kernel's per-lane march), and for jobs on
+    analytic media n_oracle sampled rays against the oracle under the pass
+    rule of tests/parity.py (grid media are chaotic over full paths; their
+    batch kernel is checked against the oracle by the headline record)."""
+    import oracle
+
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
+    from parity import compare
+
+    rng = np.random.default_rng(77)
+    pick = np.sort(rng.choice(len(jobs), min(n_jobs, len(jobs)), replace=False))
+    rep = {"jobs": len(pick), "rays_bitwise_checked": 0, "rays_bitwise_differ": 0,
+           "oracle_rays": 0, "oracle_fail": 0, "oracle_exempt_critical": 0,
+           "oracle_exempt_grazing": 0, "oracle_pos_err_max": 0.0, "oracle_dir_err_max": 0.0}
+    for k in pick:
+        j = jobs[k]
+        n, src, off = j["n_rays"], pools[j["medium"]], offset(j)
+        out, u32 = keep[k]
+        srv = {"P": out[0:3].numpy().T.astype(np.float64), "D": out[3:6].numpy().T.astype(np.float64)}
+        u = u32.numpy().view(np.uint32)
+        for i, key in enumerate(("status", "steps", "ntir", "nbtir", "flags")):
+            srv[key] = u[i].copy()
+        P0 = src[0:3, off:off + n].numpy().T.astype(np.float64)
+        d0 = src[3:6, off:off + n].numpy().T.astype(np.float64)
+        b = vrt.RayBatch(P0, d0, "fp32c")
+        vrt.trace(meds[j["medium"]], b, prm, "fp32c")
+        ref = b.results()
+        del b
+        same = np.ones(n, dtype=bool)
+        for key in ("P", "D", "status", "steps", "ntir", "nbtir", "flags"):
+            v = ref[key] == srv[key]
+            same &= v.all(axis=1) if v.ndim == 2 else v
+        rep["rays_bitwise_checked"] += n
+        rep["rays_bitwise_differ"] += int((~same).sum())
+        if media[j["medium"]]["kind"] != "grid":
+            idx = np.sort(rng.choice(n, min(n_oracle, n), replace=False))
+            o = oracle.trace(media[j["medium"]], (P0[idx], d0[idx]), prm)
+            r = compare(o, {key: v[idx] for key, v in srv.items()}, aperture=1.0,
+                        spec=media[j["medium"]])
+            rep["oracle_rays"] += r["n"]
+            rep["oracle_fail"] += r["fail"]
+            rep["oracle_exempt_critical"] += r["exempt_critical"]
+            rep["oracle_exempt_grazing"] += r["exempt_grazing"]
+            rep["oracle_pos_err_max"] = max(rep["oracle_pos_err_max"], r["pos_err_max"])
+            rep["oracle_dir_err_max"] = max(rep["oracle_dir_err_max"], r["dir_err_max"])
+    print(f"[served] parity: {json.dumps(rep)}", file=sys.stderr, flush=True)
+    return rep
 
 
 def served_bench(vrt, torch, args):
@@ -330,6 +387,7 @@ def served_bench(vrt, torch, args):
               "pool_peak_bytes": stats["pool_peak_bytes"], "lanes": stats["lanes"]}
     print(f"[served] fp32c: {rays / span:.4g} rays/s, p50 {served['p50_ms']:.1f} ms, "
           f"p99 {served['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    served["parity"] = served_parity(vrt, torch, jobs, keep, pools, meds, media, prm, offset)
     del keep
     # the same stream, one FP64 launch per job, FIFO on one stream
     stream = torch.cuda.current_stream()
@@ -629,14 +687,142 @@ def helix_bench(vrt, torch, args, n_batch=196608):
     return out
 
 
+def grid_parity(vrt, torch, med, spec, rays, prm, g_full, oracle_full, idx_full, threads):
+    """Parity of the timed grid launch configuration against the oracle.  The
+    quantized grid is chaotic for the discrete march (a 1e-13 shift of a
+    launch moves a third of the oracle's own exits by more than 1e-4), so:
+    per ray over the first 128 moves (the whole batch re-run with
+    max_steps = 128, a seeded sample of 4,096 rays recomputed by the oracle;
+    rays whose own oracle state moves under a 1e-9 launch shift are counted
+    and set aside), and two-sample statistics of the full exit states of the
+    oracle sample (the cpu_baseline rays) against the same rays of the timed
+    run."""
+    import oracle
+
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
+    from parity import compare, exempt, ill_conditioned, stat_compare
+
+    P0, d0 = rays
+    n = P0.shape[0]
+    p128 = dict(prm, max_steps=128)
+    b = vrt.RayBatch(P0, d0, "fp32c")
+    vrt.trace(med, b, p128, "fp32c")
+    g128 = b.results()
+    del b
+    idx = np.sort(np.random.default_rng(2025).choice(n, 4096, replace=False))
+    sub = {k: v[idx] for k, v in g128.items()}
+    rs = (P0[idx], d0[idx])
+
+    def orc(*a):
+        return oracle.trace(*a, n_threads=threads)
+
+    o = orc(spec, rs, p128)
+    bad = ill_conditioned(orc, spec, rs, p128)
+    rep = compare(exempt(o, bad), exempt(sub, bad), aperture=1.0, spec=spec)
+    keys = ("n", "checked", "fail", "exempt_critical", "exempt_grazing", "status_mismatch",
+            "tir_mismatch", "btir_mismatch", "pos_fail", "dir_fail", "steps_mismatch",
+            "pos_err_max", "pos_err_p99", "dir_err_max", "dir_err_p99")
+    first = {k: rep[k] for k in keys}
+    first["ill_conditioned"] = int(bad.sum())
+    first["sample"] = "4096 seeded rays of the 4M batch, first 128 moves each, per ray"
+    st = stat_compare(oracle_full, {k: v[idx_full] for k, v in g_full.items()})
+    st["sample"] = f"{len(idx_full)} rays (the cpu_baseline sample), full paths"
+    return {"first_128_moves": first, "full_path_statistics": st}
+
+
+def batch_record(vrt, torch, ctx, name, args, cpu=True):
+    """One batch workload: timed traces, roofline, FP64 GPU march, the oracle's
+    rate on a sample of the same rays and the parity of the timed results."""
+    spec, rays, prm, precision, desc, aperture = build_workload(name, args.rays)
+    n_rays = rays[0].shape[0]
+    print(f"[bench] {name}: workload ready, {n_rays} rays", file=sys.stderr, flush=True)
+    med = vrt.Medium(ctx, spec)
+    batch = vrt.RayBatch(rays[0], rays[1], precision)
+    wall, per = time_traces(vrt, torch, med, batch, prm, precision, args.steps, args.warmup)
+    cnt = vrt.counters(ctx, batch)
+    g_res = batch.results()
+    ms = float(np.mean(per))
+    ray_steps = cnt["steps"]
+    value = ray_steps / (ms / 1e3)
+    print(f"[bench] {name}: {args.steps} traces, {ms:.3f} ms each, {value:.4g} ray-steps/s",
+          file=sys.stderr, flush=True)
+    fp64_gpu = None
+    if not args.no_fp64_gpu and precision != "fp64":
+        b64 = vrt.RayBatch(rays[0], rays[1], "fp64")
+        w64, per64 = time_traces(vrt, torch, med, b64, prm, "fp64", max(2, args.steps // 5), 1)
+        c64 = vrt.counters(ctx, b64)
+        fp64_gpu = {"ms_per_step": round(float(np.mean(per64)), 3),
+                    "ray_steps_per_s": c64["steps"] / (float(np.mean(per64)) / 1e3),
+                    "note": "plain FP64 GPU march, one lane per ray, one launch per batch"}
+        del b64
+    flops = algo_flops_per_step(name) * ray_steps
+    achieved = flops / (ms / 1e3) / 1e12
+    peak = PEAK_FP32_TFLOPS if precision == "fp32c" else PEAK_FP64_TFLOPS
+    kernel = "march_fp32c_kernel" if precision == "fp32c" else "march_fp64_kernel"
+    valu = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "algo_flops_per_ray_step": algo_flops_per_step(name)}
+    if name in FP64_FLOPS_PER_STEP:
+        # FP64 and FP32 work share the vector ALU: price both in FP64 time
+        # (an FP32 flop costs PEAK_FP64 / PEAK_FP32 of an FP64 flop)
+        f64 = FP64_FLOPS_PER_STEP[name]
+        eq = f64 + algo_flops_per_step(name) * PEAK_FP64_TFLOPS / PEAK_FP32_TFLOPS
+        achieved = eq * ray_steps / (ms / 1e3) / 1e12
+        valu.update({"achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                     "algo_fp64_flops_per_ray_step": f64,
+                     "note": "FP64-equivalent rate: FP64 flops plus FP32 flops x 78.6/157.3"})
+    traffic = traffic_bytes(name) if precision == "fp32c" else None
+    if name == "grid":
+        # discretized media: the corner records of each visited cell from memory
+        bps = algo_bytes_per_step("grid")
+        gbs = bps * ray_steps / (ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "algo_bytes_per_ray_step": round(bps, 3), "kernel": kernel, "valu_side": valu}
+    else:
+        roof = dict(valu, traffic=traffic, kernel=kernel)
+    rec = {"value": value, "unit": "ray-steps/s", "ms_per_step": round(ms, 4),
+           "dtype": "f32" if precision == "fp32c" else "f64",
+           "config": {"workload": desc, "rays": n_rays, "ray_steps_per_trace": ray_steps,
+                      "dL0": prm["dL0"], "max_steps": prm["max_steps"]},
+           "wall_s": round(wall, 3), "roofline": roof, "counters": cnt}
+    if fp64_gpu:
+        rec["fp64_gpu_march"] = fp64_gpu
+    if cpu and not args.no_cpu_baseline:
+        sample = args.cpu_sample or CPU_SAMPLE.get(name, 524288)
+        base, par, extra = cpu_baseline(spec, rays, prm, sample, g_res, aperture)
+        rec["cpu_baseline"] = base
+        if name == "grid":
+            threads = base["cores"]
+            rec["parity_vs_oracle"] = grid_parity(vrt, torch, med, spec, rays, prm, g_res,
+                                                  extra[0], extra[1], threads)
+        else:
+            rec["parity_vs_oracle"] = par
+    med.close()
+    return rec
+
+
+# oracle sample per workload: about 10-30 s of host work on 16 threads
+CPU_SAMPLE = {"zernike": 32768, "spherical": 65536, "grid": 262144, "freeform": 524288}
+
+
+def header(args, rec):
+    out = {"metric": METRIC, "value": rec["value"], "unit": "ray-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": rec["dtype"], "data": "synthetic"}
+    out.update({k: v for k, v in rec.items() if k not in out})
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="freeform",
-                    choices=["freeform", "grid", "luneburg", "zernike", "spherical", "helix",
-                             "served", "n2p", "adjoint"])
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "freeform", "grid", "luneburg", "zernike", "spherical",
+                             "helix", "served", "n2p", "adjoint"])
     ap.add_argument("--jobs", type=int, default=120, help="served: jobs in the arrival stream")
     ap.add_argument("--load", type=float, default=0.8,
                     help="served: offered load as a fraction of the measured capacity")
@@ -645,6 +831,7 @@ def main(argv=None):
                     help="rays of the oracle sample (default: about 10-30 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-gpu", action="store_true")
+    ap.add_argument("--no-served", action="store_true", help="headline: skip the served record")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the march shards over rays with no exchange, and this "
@@ -670,72 +857,24 @@ def main(argv=None):
     if args.workload == "helix":
         print(json.dumps(helix_bench(vrt, torch, args)), flush=True)
         return 0
-    spec, rays, prm, precision, desc, aperture = build_workload(args.workload, args.rays)
-    n_rays = rays[0].shape[0]
-    print(f"[bench] workload ready: {n_rays} rays", file=sys.stderr, flush=True)
-
     ctx = vrt.Context(0)
-    med = vrt.Medium(ctx, spec)
-    batch = vrt.RayBatch(rays[0], rays[1], precision)
-    wall, per = time_traces(vrt, torch, med, batch, prm, precision, args.steps, args.warmup)
-    cnt = vrt.counters(ctx, batch)
-    g_res = batch.results()
-    ms = float(np.mean(per))
-    ray_steps = cnt["steps"]
-    value = ray_steps / (ms / 1e3)
-    print(f"[bench] {args.steps} traces, {ms:.3f} ms each, {value:.4g} ray-steps/s",
-          file=sys.stderr, flush=True)
-
-    fp64_gpu = None
-    if not args.no_fp64_gpu and precision != "fp64":
-        b64 = vrt.RayBatch(rays[0], rays[1], "fp64")
-        w64, per64 = time_traces(vrt, torch, med, b64, prm, "fp64", max(2, args.steps // 5), 1)
-        c64 = vrt.counters(ctx, b64)
-        fp64_gpu = {"ms_per_step": round(float(np.mean(per64)), 3),
-                    "ray_steps_per_s": c64["steps"] / (float(np.mean(per64)) / 1e3),
-                    "note": "plain FP64 GPU march, one lane per ray, one launch per batch"}
-        del b64
-
-    flops = algo_flops_per_step(args.workload) * ray_steps
-    achieved = flops / (ms / 1e3) / 1e12
-    peak = PEAK_FP32_TFLOPS if precision == "fp32c" else PEAK_FP64_TFLOPS
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": traffic_bytes(args.workload) if precision == "fp32c" else None,
-            "algo_flops_per_ray_step": algo_flops_per_step(args.workload),
-            "kernel": "march_fp32c_kernel" if precision == "fp32c" else "march_fp64_kernel"}
-    if args.workload in FP64_FLOPS_PER_STEP:
-        # FP64 and FP32 work share the vector ALU: price both in FP64 time
-        # (an FP32 flop costs PEAK_FP64 / PEAK_FP32 of an FP64 flop)
-        f64 = FP64_FLOPS_PER_STEP[args.workload]
-        eq = f64 + algo_flops_per_step(args.workload) * PEAK_FP64_TFLOPS / PEAK_FP32_TFLOPS
-        achieved = eq * ray_steps / (ms / 1e3) / 1e12
-        roof.update({"achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                     "algo_fp64_flops_per_ray_step": f64,
-                     "note": "FP64-equivalent rate: FP64 flops plus FP32 flops x 78.6/157.3"})
-    if args.workload == "grid":
-        gbs = algo_bytes_per_step("grid") * ray_steps / (ms / 1e3) / 1e9
-        roof["hbm_side"] = {"achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                            "frac": round(gbs / PEAK_HBM_GBS, 4)}
-
-    out = {"metric": METRIC, "value": value, "unit": "ray-steps/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32" if precision == "fp32c" else "f64", "data": "synthetic",
-           "config": {"workload": desc, "rays": n_rays, "ray_steps_per_trace": ray_steps,
-                      "dL0": prm["dL0"], "max_steps": prm["max_steps"]},
-           "wall_s": round(wall, 3), "roofline": roof, "counters": cnt}
-    if fp64_gpu:
-        out["fp64_gpu_march"] = fp64_gpu
-    if not args.no_cpu_baseline:
-        sample = args.cpu_sample or {"zernike": 32768, "spherical": 65536}.get(args.workload,
-                                                                                524288)
-        base, par = cpu_baseline(spec, rays, prm, sample, g_res, aperture)
-        out["cpu_baseline"] = base
-        out["parity_vs_oracle"] = par
-    med.close()
+    if args.workload != "headline":
+        out = header(args, batch_record(vrt, torch, ctx, args.workload, args))
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return 0
+    # headline: the largest single-GPU configuration (4M rays through the
+    # 256^3 quantized grid), with the freeform configuration and the served
+    # mix as sub-records
+    grid_args = argparse.Namespace(**vars(args))
+    grid_args.rays = None
+    out = header(args, batch_record(vrt, torch, ctx, "grid", grid_args))
+    ff_args = argparse.Namespace(**vars(args))
+    ff_args.rays = None
+    out["freeform"] = batch_record(vrt, torch, ctx, "freeform", ff_args)
     ctx.close()
+    if not args.no_served:
+        out["served"] = served_bench(vrt, torch, args)
     print(json.dumps(out), flush=True)
     return 0
 

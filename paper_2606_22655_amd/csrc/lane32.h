@@ -80,79 +80,48 @@ __device__ __forceinline__ void step_len64(double v, float &Dh, float &Dl) {
     Dl = (float)(v - (double)Dh);
 }
 
-// Discretized medium: cached records of the 8 corners of the current cell.
+// Discretized medium: the current cell, its origin and its 8 corner records.
 struct GridCache {
-    int ci, cj, ck;
+    int ci, cj, ck;             // cell indices; ci < 0: none (locate in double)
+    float ox, oy, oz;           // cell origin lo + c h as float pairs: head ...
+    float olx, oly, olz;        //   ... and low part
     float4 v[8];  // node records (n, h_x, h_y, h_z) at corner dx + 2 dy + 4 dz
 };
+
+// Forget the cached cell (the position jumped: entry, surface event).
+__device__ __forceinline__ void grid_invalidate(GridCache &gc) {
+    gc.ci = -1;
+    gc.ox = gc.oy = gc.oz = __builtin_nanf("");
+}
 
 struct Lane {
     float Phx, Phy, Phz, Pcx, Pcy, Pcz;  // position P = Ph - Pc
     float Ihx, Ihy, Ihz, Icx, Icy, Icz;  // direction I = Ih - Ic
     float sx, sy, sz;                    // last move P_i - P_{i-1}
-    float nlb;                           // n(P_{i-1}) = nlb + nld (grid: cell base value
-    double nld;                          //   + offset inside the cell; media taken in double:
-                                         //   the double index split; other media: nld = 0)
+    float nlb;                           // n(P_{i-1}) = nlb + nld (media taken in double:
+    double nld;                          //   the double index split; other media: nld = 0)
+    float nlo;                           // grid: n(P_{i-1}) = nlb + nlo (base node value +
+                                         //   offset inside the cell)
     float Delta, Dl;                     // pending move length Delta + Dl
     uint32_t r, steps, ntir, nbtir, flags;
     bool pending;                        // R = I and Delta set by an event: move without deciding
 };
 
-// Trilinear blend of the cached records at the fractional position: the
-// index offset from the cell's base value v000 in double (weights from the
-// double coordinates, node differences exact in float), and the gradient
-// (node differences per spacing) in single precision.
-__device__ __forceinline__ void grid_blend(const GridCache &gc, double fx, double fy, double fz,
-                                           double &delta, float &gx, float &gy, float &gz) {
-    const float base = gc.v[0].x;
-    double e[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const double a = (double)(gc.v[2 * q].x - base);  // exact: nearby float values
-        const double b = (double)(gc.v[2 * q + 1].x - base);
-        e[q] = a + fx * (b - a);
-    }
-    const double b0 = e[0] + fy * (e[1] - e[0]), b1 = e[2] + fy * (e[3] - e[2]);
-    delta = b0 + fz * (b1 - b0);
-    const float ffx = (float)fx, ffy = (float)fy, ffz = (float)fz;
-    float gxa[4], gya[4], gza[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float4 a = gc.v[2 * q], c = gc.v[2 * q + 1];
-        gxa[q] = a.y + ffx * (c.y - a.y);
-        gya[q] = a.z + ffx * (c.z - a.z);
-        gza[q] = a.w + ffx * (c.w - a.w);
-    }
-    const float gx0 = gxa[0] + ffy * (gxa[1] - gxa[0]), gx1 = gxa[2] + ffy * (gxa[3] - gxa[2]);
-    const float gy0 = gya[0] + ffy * (gya[1] - gya[0]), gy1 = gya[2] + ffy * (gya[3] - gya[2]);
-    const float gz0 = gza[0] + ffy * (gza[1] - gza[0]), gz1 = gza[2] + ffy * (gza[3] - gza[2]);
-    gx = gx0 + ffz * (gx1 - gx0);
-    gy = gy0 + ffz * (gy1 - gy0);
-    gz = gz0 + ffz * (gz1 - gz0);
-}
-
-// Cell and fractional coordinates of P = ph - pc.  Done in double: in float a
-// coordinate near 1 carries ~6e-8 of rounding, 1.5e-5 of a 256^3 cell, and
-// the trilinear gradient can change by its own size across one cell.
-__device__ __forceinline__ void grid_locate(const MediumDev &m, float phx, float phy, float phz,
-                                            float pcx, float pcy, float pcz, int &ci, int &cj,
-                                            int &ck, double &fx, double &fy, double &fz) {
-    const double u = ((double)phx - (double)pcx - m.lo[0]) * m.inv_h[0];
-    const double v = ((double)phy - (double)pcy - m.lo[1]) * m.inv_h[1];
-    const double w = ((double)phz - (double)pcz - m.lo[2]) * m.inv_h[2];
-    ci = min(max((int)floor(u), 0), m.nx - 2);
-    cj = min(max((int)floor(v), 0), m.ny - 2);
-    ck = min(max((int)floor(w), 0), m.nz - 2);
-    fx = u - (double)ci;
-    fy = v - (double)cj;
-    fz = w - (double)ck;
-}
-
-__device__ __forceinline__ void grid_fetch(const MediumDev &m, const float4 *__restrict__ rec, GridCache &gc, int ci, int cj,
-                                           int ck) {
+// Load cell (ci, cj, ck): its origin (double, kept as a float pair) and the
+// records of its 8 corners.
+__device__ __forceinline__ void grid_fetch(const MediumDev &m, const float4 *__restrict__ rec,
+                                           GridCache &gc, int ci, int cj, int ck) {
     gc.ci = ci;
     gc.cj = cj;
     gc.ck = ck;
+    const double ox = m.lo[0] + (double)ci * m.h[0], oy = m.lo[1] + (double)cj * m.h[1],
+                 oz = m.lo[2] + (double)ck * m.h[2];
+    gc.ox = (float)ox;
+    gc.oy = (float)oy;
+    gc.oz = (float)oz;
+    gc.olx = (float)(ox - (double)gc.ox);
+    gc.oly = (float)(oy - (double)gc.oy);
+    gc.olz = (float)(oz - (double)gc.oz);
     const size_t sx = 1, sy = (size_t)m.nx, sz = (size_t)m.nx * m.ny;
     const size_t o = (size_t)ck * sz + (size_t)cj * sy + ci;
 #pragma unroll
@@ -160,61 +129,95 @@ __device__ __forceinline__ void grid_fetch(const MediumDev &m, const float4 *__r
         gc.v[j] = rec[o + (j & 1) * sx + ((j >> 1) & 1) * sy + ((j >> 2) & 1) * sz];
 }
 
-// n, grad n and n(P_i) - n(P_{i-1}) for the discretized medium.  The index
-// is kept as cell base value + offset (nb, nd): the base is a node value and
-// the offset is accurate to double rounding, so the difference to the
-// previous point's (nlb, nld) keeps full precision within and across cells.
-__device__ __forceinline__ void grid32(const MediumDev &m, const float4 *__restrict__ rec, GridCache &gc, float px, float py, float pz,
-                                       float pcx, float pcy, float pcz, float nlb, double nld,
-                                       float &n, float &nb, double &nd, float &gx, float &gy,
-                                       float &gz, float &dn) {
-    int ci, cj, ck;
-    double fx, fy, fz;
-    grid_locate(m, px, py, pz, pcx, pcy, pcz, ci, cj, ck, fx, fy, fz);
-    if (ci != gc.ci || cj != gc.cj || ck != gc.ck) grid_fetch(m, rec, gc, ci, cj, ck);
-    double delta;
-    grid_blend(gc, fx, fy, fz, delta, gx, gy, gz);
-    gx *= m.finv_h[0];  // records hold node differences per node spacing
-    gy *= m.finv_h[1];
-    gz *= m.finv_h[2];
-    nb = gc.v[0].x;
-    nd = delta;
-    n = (float)((double)nb + nd);
-    dn = (float)((double)(nb - nlb) + (nd - nld));  // nb - nlb exact: nearby node values
+// Fractional coordinate of P = ph - pc along one axis of the cell whose
+// origin is o + ol: ph - o is exact or rounds at the cell's scale (the two lie
+// within about a cell of each other), and the low parts are folded in at that
+// scale, so f carries ~1e-7 of a cell -- without a double in the common step.
+__device__ __forceinline__ float cell_frac(float ph, float pc, float o, float ol, float inv_h) {
+    return (((ph - o) - ol) - pc) * inv_h;
 }
 
-// n and grad n in double at P from the cell records (exact node differences
-// per spacing): the cached cell when P lies in it, else the cell is loaded.
-__device__ inline void grid_eval64(const MediumDev &m, const float4 *__restrict__ rec, const GridCache &gc, d3 P, double &n,
-                                   d3 &g) {
-    const int nn[3] = {m.nx, m.ny, m.nz};
+// Cell of P and the fractional coordinates in it.  A step moves P by much
+// less than a cell, so when P leaves the cached cell the cell index shifts by
+// floor(f) along each axis; after an event (no cell cached: the origin is
+// NaN, so every f fails the test) P is located in double.  Indices are
+// clamped to the grid, where P itself is clamped (a point on the upper faces
+// has f = 1 in the last cell).
+__device__ __forceinline__ void grid_cell(const MediumDev &m, const float4 *__restrict__ rec,
+                                          GridCache &gc, const Lane &L, float &fx, float &fy,
+                                          float &fz) {
+    fx = cell_frac(L.Phx, L.Pcx, gc.ox, gc.olx, m.finv_h[0]);
+    fy = cell_frac(L.Phy, L.Pcy, gc.oy, gc.oly, m.finv_h[1]);
+    fz = cell_frac(L.Phz, L.Pcz, gc.oz, gc.olz, m.finv_h[2]);
+    if (fx >= 0.0f && fx < 1.0f && fy >= 0.0f && fy < 1.0f && fz >= 0.0f && fz < 1.0f) return;
+    int ci, cj, ck;
+    if (gc.ci < 0) {
+        ci = (int)floor(((double)L.Phx - (double)L.Pcx - m.lo[0]) * m.inv_h[0]);
+        cj = (int)floor(((double)L.Phy - (double)L.Pcy - m.lo[1]) * m.inv_h[1]);
+        ck = (int)floor(((double)L.Phz - (double)L.Pcz - m.lo[2]) * m.inv_h[2]);
+    } else {
+        ci = gc.ci + (int)floorf(fx);
+        cj = gc.cj + (int)floorf(fy);
+        ck = gc.ck + (int)floorf(fz);
+    }
+    ci = min(max(ci, 0), m.nx - 2);
+    cj = min(max(cj, 0), m.ny - 2);
+    ck = min(max(ck, 0), m.nz - 2);
+    if (ci != gc.ci || cj != gc.cj || ck != gc.ck) {
+        grid_fetch(m, rec, gc, ci, cj, ck);
+        fx = cell_frac(L.Phx, L.Pcx, gc.ox, gc.olx, m.finv_h[0]);
+        fy = cell_frac(L.Phy, L.Pcy, gc.oy, gc.oly, m.finv_h[1]);
+        fz = cell_frac(L.Phz, L.Pcz, gc.oz, gc.olz, m.finv_h[2]);
+    }
+    // P clamped to the grid (the tangential rule's probe may step outside)
+    fx = fminf(fmaxf(fx, 0.0f), 1.0f);
+    fy = fminf(fmaxf(fy, 0.0f), 1.0f);
+    fz = fminf(fmaxf(fz, 0.0f), 1.0f);
+}
+
+// Trilinear blend of the cached records at (fx, fy, fz): the index as an
+// offset from the cell's first node value (the node differences are exact in
+// float for nearby values), and the gradient's node differences per spacing.
+__device__ __forceinline__ void grid_blend(const GridCache &gc, float fx, float fy, float fz,
+                                           float &delta, float &gx, float &gy, float &gz) {
+    const float base = gc.v[0].x;
+    float e[4], gxa[4], gya[4], gza[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float4 a = gc.v[2 * q], c = gc.v[2 * q + 1];
+        const float da = a.x - base, dc = c.x - base;
+        e[q] = da + fx * (dc - da);
+        gxa[q] = a.y + fx * (c.y - a.y);
+        gya[q] = a.z + fx * (c.z - a.z);
+        gza[q] = a.w + fx * (c.w - a.w);
+    }
+    const float b0 = e[0] + fy * (e[1] - e[0]), b1 = e[2] + fy * (e[3] - e[2]);
+    delta = b0 + fz * (b1 - b0);
+    const float gx0 = gxa[0] + fy * (gxa[1] - gxa[0]), gx1 = gxa[2] + fy * (gxa[3] - gxa[2]);
+    const float gy0 = gya[0] + fy * (gya[1] - gya[0]), gy1 = gya[2] + fy * (gya[3] - gya[2]);
+    const float gz0 = gza[0] + fy * (gza[1] - gza[0]), gz1 = gza[2] + fy * (gza[3] - gza[2]);
+    gx = gx0 + fz * (gx1 - gx0);
+    gy = gy0 + fz * (gy1 - gy0);
+    gz = gz0 + fz * (gz1 - gz0);
+}
+
+// n at P in double from the node values (trilinear, P clamped to the grid):
+// the index at surface events and at the tangential rule's probe.
+__device__ inline double grid_index64(const MediumDev &m, d3 P) {
     int c[3];
     double f[3];
-    for (int a = 0; a < 3; ++a) {
-        double x = get(P, a);
-        x = x < m.lo[a] ? m.lo[a] : (x > m.hi[a] ? m.hi[a] : x);
-        const double u = (x - m.lo[a]) / m.h[a];
-        int ci = (int)floor(u);
-        ci = ci < 0 ? 0 : (ci > nn[a] - 2 ? nn[a] - 2 : ci);
-        c[a] = ci;
-        f[a] = u - (double)ci;
-    }
-    const bool cached = c[0] == gc.ci && c[1] == gc.cj && c[2] == gc.ck;
+    grid_cell64(m, P, c, f);
     const size_t sy = (size_t)m.nx, sz = (size_t)m.nx * m.ny;
     const size_t o = (size_t)c[2] * sz + (size_t)c[1] * sy + c[0];
-    n = 0.0;
-    g = mk(0, 0, 0);
-    for (int j = 0; j < 8; ++j) {
-        const float4 r = cached ? gc.v[j]
-                                : rec[o + (j & 1) + ((j >> 1) & 1) * sy + ((j >> 2) & 1) * sz];
-        const double w = ((j & 1) ? f[0] : 1.0 - f[0]) * ((j & 2) ? f[1] : 1.0 - f[1]) *
-                         ((j & 4) ? f[2] : 1.0 - f[2]);
-        n += w * (double)r.x;
-        g.x += w * (double)r.y;
-        g.y += w * (double)r.z;
-        g.z += w * (double)r.w;
-    }
-    g = mk(g.x / m.h[0], g.y / m.h[1], g.z / m.h[2]);
+    double n = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *
+                                 (dz ? f[2] : 1.0 - f[2]);
+                n += w * (double)m.grid[o + dx + dy * sy + dz * sz];
+            }
+    return n;
 }
 
 template <int MK>
@@ -236,24 +239,19 @@ __device__ __forceinline__ void write_out(const RaysDev<float> &io, const Lane &
 
 // Index at a surface point in the representation the march keeps.
 template <int MK>
-__device__ __forceinline__ void index_at_event(const MediumDev &m, const float4 *__restrict__ rec, GridCache &gc, d3 P,
-                                               float &nlb,
-                                               double &nld) {
+__device__ __forceinline__ void index_at_event(const MediumDev &m, GridCache &gc, d3 P, Lane &L) {
     if constexpr (MK == VRT_MEDIUM_GRID) {
-        float n, gx, gy, gz, dn;
-        gc.ci = -1;
-        float phx, phy, phz, pcx, pcy, pcz;
-        split(P.x, phx, pcx);
-        split(P.y, phy, pcy);
-        split(P.z, phz, pcz);
-        grid32(m, rec, gc, phx, phy, phz, pcx, pcy, pcz, 0.f, 0.0, n, nlb, nld, gx, gy, gz, dn);
+        grid_invalidate(gc);
+        const double n = grid_index64(m, P);
+        L.nlb = (float)n;
+        L.nlo = (float)(n - (double)L.nlb);
     } else if constexpr (kIndexIn64<MK>) {
         const double n = index64<MK>(m, P);
-        nlb = (float)n;
-        nld = n - (double)nlb;
+        L.nlb = (float)n;
+        L.nld = n - (double)L.nlb;
     } else {
-        nlb = (float)index64<MK>(m, P);
-        nld = 0.0;
+        L.nlb = (float)index64<MK>(m, P);
+        L.nld = 0.0;
     }
 }
 
@@ -280,7 +278,7 @@ __device__ bool lane_init(const MediumDev &m, const float4 *__restrict__ rec, co
         split(I.x, L.Ihx, L.Icx);
         split(I.y, L.Ihy, L.Icy);
         split(I.z, L.Ihz, L.Icz);
-        index_at_event<MK>(m, rec, gc, P0, L.nlb, L.nld);
+        index_at_event<MK>(m, gc, P0, L);
         L.pending = false;
         return true;
     }
@@ -308,10 +306,94 @@ __device__ bool lane_init(const MediumDev &m, const float4 *__restrict__ rec, co
     split(R.x, L.Ihx, L.Icx);
     split(R.y, L.Ihy, L.Icy);
     split(R.z, L.Ihz, L.Icz);
-    index_at_event<MK>(m, rec, gc, P, L.nlb, L.nld);
+    index_at_event<MK>(m, gc, P, L);
     step_len64(t.dL0 / n_in, L.Delta, L.Dl);
     L.pending = true;
     return true;
+}
+
+// The decision of one step in a discretized medium, in single precision:
+// the cell and fractions relative to the cached cell's origin, the trilinear
+// blend of its records, the index difference (n_i - n_{i-1} as the difference
+// of two base node values, exact, plus that of two in-cell offsets), and the
+// discriminant D = mu^2 c^2 - (mu^2 - 1) in float.  Near the critical angle D
+// is the difference of two terms of size 2 |mu - 1| ~ 1e-3 that float holds to
+// ~1e-10, which places the decision D <= 0 to ~1e-8 rad, far inside the
+// 1e-6 rad window where rays are flagged.  Refraction is the increment of
+// Eqs. (9)-(10) as for the other media; TIR reflects by -2 c N (Eq. (20)) and
+// moves on with Delta_{i-1} = dL0 / n_{i-1}.  The tangential rule probes n in
+// double from the node values.  Sets the direction increment, L.Delta, L.Dl
+// and the index of P_i as the next step's n(P_{i-1}).
+__device__ __forceinline__ void grid_decide(const MediumDev &m, const float4 *__restrict__ rec,
+                                            const TraceDev &t, Lane &L, GridCache &gc, float dL0,
+                                            float eps_tan, float crit_f, float &incx, float &incy,
+                                            float &incz) {
+    const float dL0l = (float)(t.dL0 - (double)dL0);  // dL0 = dL0 + dL0l
+    float fx, fy, fz, delta, gx, gy, gz;
+    grid_cell(m, rec, gc, L, fx, fy, fz);
+    grid_blend(gc, fx, fy, fz, delta, gx, gy, gz);
+    gx *= m.finv_h[0];  // records hold node differences per node spacing
+    gy *= m.finv_h[1];
+    gz *= m.finv_h[2];
+    const float nb = gc.v[0].x;
+    const float ni = nb + delta, nl = (nb - ni) + delta;  // n(P_i) = ni + nl
+    const float dn = (nb - L.nlb) + (delta - L.nlo);      // nb - nlb exact: nearby node values
+    incx = incy = incz = 0.0f;
+    const float gl2 = gx * gx + gy * gy + gz * gz;
+    if (!(gl2 > 0.0f) || !isfinite(gl2)) {  // cases (ii)/(iii): straight
+        step_len(dL0, dL0l, ni, nl, L.Delta, L.Dl);
+        L.flags |= VRT_FLAG_STRAIGHT;
+    } else {
+        const float inv = rsqrtf(gl2);
+        const float Nx = gx * inv, Ny = gy * inv, Nz = gz * inv;  // Eq. (5)
+        const float c = (Nx * L.Ihx + Ny * L.Ihy + Nz * L.Ihz) -
+                        (Nx * L.Icx + Ny * L.Icy + Nz * L.Icz);
+        if (fabsf(c) <= eps_tan) {
+            // case (iv): arc with curvature grad n / n, Eqs. (16)-(18); n at the
+            // probe P + Delta N in double
+            step_len(dL0, dL0l, ni, nl, L.Delta, L.Dl);
+            const double D64 = (double)L.Delta + (double)L.Dl;
+            const d3 Q = mk((double)L.Phx - L.Pcx + D64 * Nx, (double)L.Phy - L.Pcy + D64 * Ny,
+                            (double)L.Phz - L.Pcz + D64 * Nz);
+            const float dnp = (float)(grid_index64(m, Q) - ((double)nb + (double)delta));
+            const float a = dnp * frcp(2.0f * ni);
+            const float w = fsqrt(fmaxf(0.0f, 1.0f - a * a));
+            const float k = -a * a / (1.0f + w);  // sqrt(1-a^2) - 1 without cancellation
+            incx = k * L.Ihx + a * Nx;
+            incy = k * L.Ihy + a * Ny;
+            incz = k * L.Ihz + a * Nz;
+            L.flags |= VRT_FLAG_TANGENT;
+        } else {
+            const float m1 = -dn * frcp(ni);  // mu_i - 1, mu_i = n_{i-1} / n_i
+            const float muf = 1.0f + m1;
+            const float D = muf * muf * c * c - m1 * (2.0f + m1);
+            if (m1 > 0.0f && fabsf(D) < 2.02f * muf * muf * crit_f) {
+                const double mu = 1.0 + (double)m1, cd = (double)c;
+                const double Dd = mu * mu * cd * cd - (double)m1 * (2.0 + (double)m1);
+                if (near_critical(mu, cd, Dd, t.crit_rad)) L.flags |= VRT_FLAG_NEAR_CRITICAL;
+            }
+            if (m1 < 0.0f && fabsf(c) < crit_f) L.flags |= VRT_FLAG_NEAR_GRAZING;
+            if (D <= 0.0f) {  // case (v): reflect, move on with Delta_{i-1} (Eq. (20))
+                const float c2 = -2.0f * c;
+                incx = c2 * Nx;
+                incy = c2 * Ny;
+                incz = c2 * Nz;
+                const float nph = L.nlb + L.nlo, npl = (L.nlb - nph) + L.nlo;
+                step_len(dL0, dL0l, nph, npl, L.Delta, L.Dl);
+                L.ntir++;
+            } else {  // Eqs. (9)-(10) as an increment
+                const float sD = fsqrt(D);
+                const float q = m1 * (2.0f + m1) * frcp(sD + muf * fabsf(c));
+                const float gam = c > 0.0f ? -q : q;  // -sgn(c) q, q signed
+                incx = m1 * L.Ihx + gam * Nx;
+                incy = m1 * L.Ihy + gam * Ny;
+                incz = m1 * L.Ihz + gam * Nz;
+                step_len(dL0, dL0l, ni, nl, L.Delta, L.Dl);
+            }
+        }
+    }
+    L.nlb = nb;
+    L.nlo = delta;
 }
 
 // One decision (unless pending) and one move.  Returns false when the ray
@@ -322,17 +404,20 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
                                           const TraceDev &t, const RaysDev<float> &io, Lane &L,
                                           GridCache &gc, float dL0, float eps_tan, float mrg,
                                           float crit_f) {
-    if (!L.pending) {
+    if constexpr (MK == VRT_MEDIUM_GRID) {
+        if (!L.pending) {
+            float incx, incy, incz;
+            grid_decide(m, rec, t, L, gc, dL0, eps_tan, crit_f, incx, incy, incz);
+            kahan_add(L.Ihx, L.Icx, incx);
+            kahan_add(L.Ihy, L.Icy, incy);
+            kahan_add(L.Ihz, L.Icz, incz);
+        }
+    } else if (!L.pending) {
         const float dL0l = (float)(t.dL0 - (double)dL0);  // dL0 = dL0 + dL0l
         float ni, gx, gy, gz, dn, nb = 0.f, nl = 0.f;
         double nd = 0.0;
-        float n_last = L.nlb;  // float-evaluated analytic media keep nld = 0
-        if constexpr (MK == VRT_MEDIUM_GRID) n_last = (float)((double)L.nlb + L.nld);
-        if constexpr (MK == VRT_MEDIUM_GRID) {
-            grid32(m, rec, gc, L.Phx, L.Phy, L.Phz, L.Pcx, L.Pcy, L.Pcz, L.nlb, L.nld, ni, nb, nd, gx,
-                   gy, gz, dn);
-            nl = (float)(((double)nb + nd) - (double)ni);
-        } else if constexpr (kIndexIn64<MK>) {
+        const float n_last = L.nlb;  // float-evaluated analytic media keep nld = 0
+        if constexpr (kIndexIn64<MK>) {
             // n and grad n in double at the compensated position; n(P_{i-1}) is
             // kept as nlb + nld, so dn is a difference of two double indices
             const d3 P64 = mk((double)L.Phx - L.Pcx, (double)L.Phy - L.Pcy, (double)L.Phz - L.Pcz);
@@ -372,13 +457,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
                 step_len(dL0, dL0l, ni, nl, Delta, Dl);
                 const float qx = Delta * Nx, qy = Delta * Ny, qz = Delta * Nz;
                 float np, dnp;
-                if constexpr (MK == VRT_MEDIUM_GRID) {
-                    float pb, px, py, pz;
-                    double pd;
-                    GridCache g2 = gc;
-                    grid32(m, rec, g2, L.Phx + qx, L.Phy + qy, L.Phz + qz, L.Pcx, L.Pcy, L.Pcz, nb, nd, np,
-                           pb, pd, px, py, pz, dnp);
-                } else if constexpr (kIndexIn64<MK>) {
+                if constexpr (kIndexIn64<MK>) {
                     const d3 Q64 = mk((double)L.Phx - L.Pcx + qx, (double)L.Phy - L.Pcy + qy,
                                       (double)L.Phz - L.Pcz + qz);
                     double nq;
@@ -411,13 +490,8 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
                                       (double)L.Ihz - L.Icz);
                     d3 g64, gp;
                     double ni64, np64;
-                    if constexpr (MK == VRT_MEDIUM_GRID) {
-                        grid_eval64(m, rec, gc, P64, ni64, g64);
-                        grid_eval64(m, rec, gc, Pp64, np64, gp);
-                    } else {
-                        med64<MK>(m, P64, ni64, g64);
-                        med64<MK>(m, Pp64, np64, gp);
-                    }
+                    med64<MK>(m, P64, ni64, g64);
+                    med64<MK>(m, Pp64, np64, gp);
                     const double gl = sqrt(dot(g64, g64));
                     const d3 N = mk(g64.x / gl, g64.y / gl, g64.z / gl);
                     const double cd = dot(N, I64);
@@ -460,7 +534,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
             }
         }
         L.nlb = nb;
-        if constexpr (MK == VRT_MEDIUM_GRID || kIndexIn64<MK>) L.nld = nd;
+        if constexpr (kIndexIn64<MK>) L.nld = nd;
         kahan_add(L.Ihx, L.Icx, incx);
         kahan_add(L.Ihy, L.Icy, incy);
         kahan_add(L.Ihz, L.Icz, incz);
@@ -516,7 +590,8 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
     d3 P = P64 + tx * R64;
     surf_snap(b, P, face);
     const d3 N = surf_normal(b, P, face);
-    const double n_last = (double)L.nlb + L.nld;
+    const double n_last =
+        (double)L.nlb + (MK == VRT_MEDIUM_GRID ? (double)L.nlo : L.nld);  // n(P_{i-1})
     const double mu = n_last / m.n_amb, c = dot(N, R64);
     const double D = 1.0 - mu * mu * (1.0 - c * c);
     if (near_critical(mu, c, D, t.crit_rad)) L.flags |= VRT_FLAG_NEAR_CRITICAL;
@@ -529,7 +604,7 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
         split(R.y, L.Ihy, L.Icy);
         split(R.z, L.Ihz, L.Icz);
         step_len64(t.dL0 / n_last, L.Delta, L.Dl);
-        index_at_event<MK>(m, rec, gc, P, L.nlb, L.nld);
+        index_at_event<MK>(m, gc, P, L);
         L.nbtir++;
         L.flags |= VRT_FLAG_BOUNDARY_TIR;
         L.pending = true;

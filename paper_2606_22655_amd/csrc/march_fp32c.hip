@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256, MK == VRT_MEDIUM_GRID || MK == VRT_MEDIUM_ZERN
     const RaysDev<float> &io = D->io;
     Lane L;
     GridCache gc;
-    gc.ci = -1;
+    grid_invalidate(gc);
     bool active = false, done = false;
     const float dL0 = (float)t.dL0;
     const float eps_tan = (float)t.eps_tan;

@@ -296,7 +296,7 @@ __device__ __attribute__((noinline)) void march_group(WaveCtx &cw, LdsDesc Dp, L
     const uint64_t below = (1ull << c.lane) - 1ull;
     Lane L;
     GridCache gc;
-    gc.ci = -1;
+    grid_invalidate(gc);
     bool active = false;
     uint64_t act = 0;              // wave mask of lanes holding a ray
     uint32_t lslot = 0;            // job slot of the lane's ray
@@ -407,7 +407,7 @@ __device__ __attribute__((noinline)) void march_group(WaveCtx &cw, LdsDesc Dp, L
         bool ended = false;
         if (fresh) {
             aslot = lslot;
-            gc.ci = -1;
+            grid_invalidate(gc);
             active = lane_init<MK>(D.m, D.m.rec, D.b, D.t, c.table[lslot].io, L, gc);
             ended = !active;
         }

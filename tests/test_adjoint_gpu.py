@@ -120,7 +120,7 @@ def fd_rays(vrt, ctx, values, flat, h, P0, d0, prm, tgt):
     rm = trace_fp64(vrt, ctx, vm.reshape(values.shape), P0, d0, prm)
     lp, _ = ray_loss(rp, tgt)
     lm, _ = ray_loss(rm, tgt)
-    sig = [(r["status"], r["ntir"], r["nbtir"]) for r in (rp, rm)]
+    sig = [(r["status"], r["ntir"], r["nbtir"], r["steps"]) for r in (rp, rm)]
     return (lp - lm) / hh, sig
 
 
@@ -141,7 +141,7 @@ def test_gradient_matches_finite_differences(vrt, ctx, problem):
     values = med["grid"]
     n = len(P0)
     base_res = trace_fp64(vrt, ctx, values, P0, d0, prm)
-    base = (base_res["status"], base_res["ntir"], base_res["nbtir"])
+    base = (base_res["status"], base_res["ntir"], base_res["nbtir"], base_res["steps"])
     nodes = np.random.default_rng(304).choice(values.size, 32, replace=False)
     checked = worst = 0.0
     set_aside = []
@@ -165,45 +165,86 @@ def test_gradient_matches_finite_differences(vrt, ctx, problem):
 
 
 def test_gradient_matches_the_oracle(vrt, ctx, orc, problem):
-    """The FP64 oracle's own difference quotients (its march, h = 1e-5 and
-    5e-6) on 8,192 of the rays, linear rays only, against the adjoint."""
+    """The FP64 oracle's own difference quotients against the adjoint at 32
+    nodes, on 8,192 of the rays.
+
+    In this medium (1 % white noise on 64^3 nodes) a parallel ray meets ~50
+    TIR decisions at near-grazing incidence, so even a small change of one
+    node value flips the branch pattern (status, TIR counts, step count) of
+    most rays crossing the node's cells; a difference quotient is meaningful
+    only on the rays whose pattern is unchanged at v +- h and v +- h/2 and
+    whose two quotients agree to 1e-3 (linear rays).  Steps h = 8 and 4 float
+    ulps of the node value keep the most rays linear.  Rays that move the
+    loss lie within 5 cells of the node across the beam (lateral drift over
+    the unit path stays below one cell), so the oracle retraces only those
+    (the adjoint of the footprint rays equals the adjoint of all rays at the
+    node, checked).  Nodes are taken in a seeded order among those the rays
+    depend on, keeping the first 32 with at least one linear ray.  Each
+    node's error is bounded against its net gradient (1e-3 of it, with a
+    floor of 1e-6 of the summed size of the rays' contributions for nodes
+    where they cancel) and against that summed size (1e-3)."""
     med, P0, d0, prm, tgt = problem
     values = med["grid"]
+    N = values.shape[0]
     sel = np.arange(0, len(P0), 2)
     P0s, d0s, tgs = P0[sel], d0[sel], tgt[sel]
     n = len(sel)
     _, g_all, _, _ = adjoint(vrt, ctx, values, P0s, d0s, prm, tgs, 1.0 / n)
-    # 6 seeded nodes among those these rays depend on
-    nodes = np.random.default_rng(305).choice(np.nonzero(g_all.ravel())[0], 6, replace=False)
-    compared = 0
+    o = orc.trace(workloads.grid_medium(values), (P0s, d0s), prm)
+    base = (o["status"], o["ntir"], o["nbtir"], o["steps"])
 
-    def oracle_q(flat, h):
+    def oracle_q(flat, h, idx):
         vp = values.copy().ravel()
         vm = values.copy().ravel()
         vp[flat] += np.float32(h)
         vm[flat] -= np.float32(h)
         hh = float(vp[flat]) - float(vm[flat])
-        rp = orc.trace(workloads.grid_medium(vp.reshape(values.shape)), (P0s, d0s), prm)
-        rm = orc.trace(workloads.grid_medium(vm.reshape(values.shape)), (P0s, d0s), prm)
-        lp, _ = ray_loss(rp, tgs)
-        lm, _ = ray_loss(rm, tgs)
-        return (lp - lm) / hh, [(r["status"], r["ntir"], r["nbtir"]) for r in (rp, rm)]
+        rp = orc.trace(workloads.grid_medium(vp.reshape(values.shape)), (P0s[idx], d0s[idx]), prm)
+        rm = orc.trace(workloads.grid_medium(vm.reshape(values.shape)), (P0s[idx], d0s[idx]), prm)
+        lp, _ = ray_loss(rp, tgs[idx])
+        lm, _ = ray_loss(rm, tgs[idx])
+        return (lp - lm) / hh, [(r["status"], r["ntir"], r["nbtir"], r["steps"]) for r in (rp, rm)]
 
-    o = orc.trace(workloads.grid_medium(values), (P0s, d0s), prm)
-    base = (o["status"], o["ntir"], o["nbtir"])
-    for flat in nodes:
-        q1, s1 = oracle_q(flat, 1e-5)
-        q2, s2 = oracle_q(flat, 5e-6)
-        lin = linear_rays(q1, q2, s1 + s2, base)
+    order = np.random.default_rng(305).permutation(np.nonzero(g_all.ravel())[0])
+    h = 8 * 1.1920929e-07
+    compared, tried = 0, 0
+    worst_net = worst_sum = 0.0
+    for flat in order[:600]:
+        if compared == 32:
+            break
+        tried += 1
+        k, j, i = np.unravel_index(flat, values.shape)
+        near = ((np.abs(P0s[:, 0] - i / (N - 1)) < 5.0 / (N - 1)) &
+                (np.abs(P0s[:, 1] - j / (N - 1)) < 5.0 / (N - 1)))
+        idx = np.nonzero(near)[0]
+        q1, s1 = oracle_q(flat, h, idx)
+        q2, s2 = oracle_q(flat, h / 2, idx)
+        lin = linear_rays(q1, q2, s1 + s2, tuple(b[idx] for b in base))
+        dep = (q1 != 0) | (q2 != 0)
+        if not (lin & dep).any():
+            continue
+        if compared < 4:  # the footprint holds every ray that reaches the node
+            _, gf, _, _ = adjoint(vrt, ctx, values, P0s[idx], d0s[idx], prm, tgs[idx], 1.0 / n)
+            assert abs(gf.ravel()[flat] - g_all.ravel()[flat]) <= 1e-12 * np.abs(g_all).max()
         qr = ((4 * q2 - q1) / 3)[lin]
         fd = qr.sum() / n
-        _, g, _, _ = adjoint(vrt, ctx, values, P0s[lin], d0s[lin], prm, tgs[lin], 1.0 / n)
-        scale = max(np.abs(qr).sum() / n, 1e-9)
-        print(f"[adjoint] oracle node {flat}: adjoint {g.ravel()[flat]:.6e} oracle fd {fd:.6e} "
-              f"(sum |per ray| {scale:.3e}, {int((~lin).sum())} rays set aside)", flush=True)
-        assert abs(g.ravel()[flat] - fd) <= 1e-3 * scale
-        compared += fd != 0.0
-    assert compared >= 3
+        li = idx[lin]
+        _, g, _, _ = adjoint(vrt, ctx, values, P0s[li], d0s[li], prm, tgs[li], 1.0 / n)
+        scale = max(np.abs(qr).sum() / n, 1e-300)
+        err = abs(g.ravel()[flat] - fd)
+        rel_net = err / max(abs(fd), 1e-300)
+        print(f"[adjoint] oracle node {flat}: adjoint {g.ravel()[flat]:.9e} oracle fd {fd:.9e} "
+              f"error / net {rel_net:.2e}, / sum |per ray| {err / scale:.2e} "
+              f"({int((lin & dep).sum())} linear of {int(dep.sum())} dependent rays)", flush=True)
+        assert err <= 1e-3 * scale
+        assert err <= 1e-3 * abs(fd) + 1e-6 * scale
+        worst_sum = max(worst_sum, err / scale)
+        if abs(fd) > 1e-3 * scale:
+            worst_net = max(worst_net, rel_net)
+        compared += 1
+    print(f"[adjoint] oracle: {compared} nodes compared ({tried} tried); worst error / net "
+          f"gradient {worst_net:.3e}, worst error / sum |per ray| {worst_sum:.3e}", flush=True)
+    assert compared == 32
 
 
 def test_checkpoint_interval_does_not_change_the_gradient(vrt, ctx, problem):
