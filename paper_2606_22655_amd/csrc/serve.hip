@@ -80,7 +80,18 @@ constexpr uint64_t kPollTicks = 200;    // 2 us at the 100 MHz wall clock betwee
 constexpr int kRanges = 4;              // job ranges one refill may draw from
 constexpr uint32_t kScan = 64;          // jobs a refill looks ahead for its group
 constexpr uint32_t kFlushEvery = 256;   // iterations between accounting flushes
-constexpr int kServeOcc = 2;            // resident blocks per CU the kernel is compiled for
+constexpr int kMaxBlocksPerCu = 4;      // wave descriptor copies are sized for this
+constexpr double kSliceSec = 0.025;     // a class's run yields after this when the other waits
+
+// Medium classes, one persistent kernel each: the marches of a class share a
+// register budget, so each class runs at the occupancy its heaviest march
+// allows (analytic media at 3 blocks per CU like the batch kernel; grids and
+// the Zernike lens, whose marches need ~215 VGPRs, at 2).
+constexpr int kClasses = 2;
+__host__ __device__ constexpr int medium_class(int kind) {
+    return kind == VRT_MEDIUM_GRID || kind == VRT_MEDIUM_ZERNIKE ? 1 : 0;
+}
+__host__ __device__ constexpr int class_occupancy(int cls) { return cls == 0 ? 3 : 2; }
 
 struct alignas(16) JobDesc {
     MediumDev m;
@@ -110,15 +121,16 @@ struct DevCtl {
     uint32_t dtail, pad0[15];
     uint32_t act, pad1[15];               // activation lock
     unsigned long long poll_t, pad2[7];   // wall clock of the last host-tail poll
-    uint32_t first_open, pad3[15];        // jobs below it have no rays to hand out
+    uint32_t first_open[kClasses][16];    // per class: jobs below it have no rays for it
     uint32_t exiting, pad4[15];           // the kernel is leaving: claim nothing more
 };
 
 // host mailbox (coherent pinned host memory), one 64-byte line each
 struct Mailbox {
     uint32_t htail, pad0[15];  // host: jobs [0, htail) are staged
-    uint32_t live, pad1[15];   // host: admitted jobs not yet retired
+    uint32_t live[kClasses][16];  // host, per class: admitted jobs not yet retired
     uint32_t stop, pad2[15];   // host: leave
+    uint32_t yield, pad4[15];  // host: the running class's kernel leaves (the other waits)
     uint32_t lost, pad3[15];   // device: a claim met a reused slot (fatal for the server)
 };
 
@@ -137,8 +149,18 @@ __device__ __forceinline__ T *rfl_ptr(T *p) {
     return (T *)(((uint64_t)hi << 32) | lo);
 }
 
-using LdsF = const __attribute__((address_space(3))) float *;
-using LdsDesc = const __attribute__((address_space(3))) JobDesc *;
+// The wave's group descriptor and bump table are read through the scalar
+// data cache, as kernel arguments are: pointers in the constant address space
+// whose value is wave-uniform.
+using ConstF = const __attribute__((address_space(4))) float *;
+using ConstDesc = const __attribute__((address_space(4))) JobDesc *;
+template <class P>
+__device__ __forceinline__ P rfl_cptr(P p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P)(((uint64_t)hi << 32) | lo);
+}
 
 // Pointers and wave-uniform progress of one wave.
 struct WaveCtx {
@@ -173,6 +195,9 @@ __device__ __forceinline__ void maybe_activate(WaveCtx &c) {
         }
     }
     if (!rfl(__shfl(go, 0))) return;
+    if (c.lane == 0 &&
+        __hip_atomic_load(&c.mb->yield, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+        __hip_atomic_store(&c.dc->exiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t ht =
         rfl(__hip_atomic_load(&c.mb->htail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
     const uint32_t dt =
@@ -264,20 +289,23 @@ __device__ __forceinline__ void flush_acc(WaveCtx &c, uint32_t aslot, uint32_t &
     }
 }
 
-// Job jj has rays to hand out (its slot still holds it).
-__device__ __forceinline__ bool claimable(const WaveCtx &c, uint32_t jj) {
+// Job jj is of medium class cls and has rays to hand out (its slot still
+// holds it).
+__device__ __forceinline__ bool claimable(const WaveCtx &c, uint32_t jj, int cls) {
     const uint32_t sl = jj % kSlots;
     const unsigned long long w =
         __hip_atomic_load(&c.ctl[sl].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return (uint32_t)(w >> 32) == jj && (uint32_t)w < c.table[sl].n;
+    return (uint32_t)(w >> 32) == jj && (uint32_t)w < c.table[sl].n &&
+           medium_class(c.table[sl].kind) == cls;
 }
 
-// March rays of the wave's group (descriptor and bump table in LDS) until
+// March rays of the wave's group (its descriptor copy and the medium's bump
+// table read as constants) until
 // the group has no rays left for it and its lanes are empty.  One function
 // per medium kind, not inlined: each gets the registers of its own march
 // (inlined side by side, the kinds' marches spill).
 template <int MK>
-__device__ __attribute__((noinline)) void march_group(WaveCtx &cw, LdsDesc Dp, LdsF B,
+__device__ __attribute__((noinline)) void march_group(WaveCtx &cw, ConstDesc Dp,
                                                       uint32_t group_in) {
     WaveCtx c;  // wave-uniform copies in scalar registers
     c.hdesc = rfl_ptr(cw.hdesc);
@@ -292,7 +320,9 @@ __device__ __attribute__((noinline)) void march_group(WaveCtx &cw, LdsDesc Dp, L
     c.seen = rfl(cw.seen);
     c.it = rfl(cw.it);
     const uint32_t group = rfl(group_in);
-    const JobDesc &D = *(const JobDesc *)Dp;
+    const ConstDesc Du = rfl_cptr(Dp);
+    const JobDesc &D = *(const JobDesc *)Du;
+    const ConstF B = rfl_cptr((ConstF)D.m.bumps_f);
     const uint64_t below = (1ull << c.lane) - 1ull;
     Lane L;
     GridCache gc;
@@ -366,7 +396,7 @@ __device__ __attribute__((noinline)) void march_group(WaveCtx &cw, LdsDesc Dp, L
                     }
                     if (gone && jj == jc) {  // nothing for anyone below jc
                         jc = jj + 1;
-                        atomicMax(&c.dc->first_open, jc);
+                        atomicMax(&c.dc->first_open[medium_class(MK)][0], jc);
                     }
                 }
                 unmet |= need;
@@ -402,8 +432,12 @@ __device__ __attribute__((noinline)) void march_group(WaveCtx &cw, LdsDesc Dp, L
             }
         }
         // a lane may only start a ray of another job once its count is accounted
-        if (__ballot(fresh && acnt && aslot != lslot) || (++c.it % kFlushEvery == 0 && __ballot(acnt)))
+        const bool periodic = ++c.it % kFlushEvery == 0;
+        if (__ballot(fresh && acnt && aslot != lslot) || (periodic && __ballot(acnt)))
             flush_acc(c, aslot, acnt, asteps);
+        // busy waves also take their turn at activating staged jobs (and at
+        // relaying the host's yield)
+        if (periodic) maybe_activate(c);
         bool ended = false;
         if (fresh) {
             aslot = lslot;
@@ -431,16 +465,13 @@ __device__ __attribute__((noinline)) void march_group(WaveCtx &cw, LdsDesc Dp, L
     }
 }
 
-__global__ __launch_bounds__(256, kServeOcc) void serve_kernel(const JobDesc *hdesc,
-                                                               JobDesc *table, JobCtl *ctl,
-                                                               DevCtl *dc, Mailbox *mb,
-                                                               DoneRec *done) {
-    __shared__ JobDesc wdesc[4];                        // the wave's group: medium, params
-    __shared__ float wbump[4][VRT_MAX_BUMPS * kBumpF];  // its bump table
+template <int kClass>
+__global__ __launch_bounds__(256, class_occupancy(kClass)) void serve_kernel(
+    const JobDesc *hdesc, JobDesc *table, JobCtl *ctl, DevCtl *dc, Mailbox *mb, DoneRec *done,
+    JobDesc *wdg) {
     __shared__ unsigned long long wacc_all[4][2];
     const int w = threadIdx.x >> 6;
-    JobDesc &D = wdesc[w];
-    const LdsF B = (LdsF)&wbump[w][0];
+    JobDesc *mine = wdg + (size_t)blockIdx.x * 4 + w;  // the wave's copy of its group descriptor
     WaveCtx c;
     c.hdesc = hdesc;
     c.table = table;
@@ -450,7 +481,8 @@ __global__ __launch_bounds__(256, kServeOcc) void serve_kernel(const JobDesc *hd
     c.done = done;
     c.wacc = wacc_all[w];
     c.lane = __lane_id();
-    c.jcur = rfl(__hip_atomic_load(&dc->first_open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    uint32_t *first_open = &dc->first_open[kClass][0];
+    c.jcur = rfl(__hip_atomic_load(first_open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     c.seen = 0;
     c.it = 0;
     uint32_t idle = 0;
@@ -460,41 +492,44 @@ __global__ __launch_bounds__(256, kServeOcc) void serve_kernel(const JobDesc *hd
         refresh_tail(c);
         if (exiting(c)) break;
         uint32_t fo =
-            rfl(__hip_atomic_load(&dc->first_open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            rfl(__hip_atomic_load(first_open, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (fo > c.jcur) c.jcur = fo;
-        while (c.jcur < c.seen && !claimable(c, c.jcur)) {
+        while (c.jcur < c.seen && !claimable(c, c.jcur, kClass)) {
             if (c.jcur == fo) {
                 fo = c.jcur + 1;
-                if (c.lane == 0) atomicMax(&dc->first_open, fo);
+                if (c.lane == 0) atomicMax(first_open, fo);
             }
             ++c.jcur;
         }
         if (c.jcur < c.seen) {
-            // adopt the job's group: its descriptor and bump table into LDS
+            // adopt the job's group: copy its descriptor to the wave's own slot
+            // (the job's table slot may be reused while the wave still marches
+            // the group's other jobs), then drop stale scalar-cache lines of
+            // that slot before march_group reads it as constants
             const uint32_t sl = c.jcur % kSlots;
             const uint4 *src = (const uint4 *)(table + sl);
-            uint4 *dst = (uint4 *)&D;
+            uint4 *dst = (uint4 *)mine;
             for (uint32_t q = c.lane; q < sizeof(JobDesc) / 16; q += 64) dst[q] = src[q];
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            const int kind = (int)rfl((uint32_t)D.kind);
-            const uint32_t nb = kind == VRT_MEDIUM_GAUSSIAN ? rfl((uint32_t)D.m.K) * kBumpF : 0u;
-            const float *bsrc = D.m.bumps_f;
-            for (uint32_t q = c.lane; q < nb; q += 64) wbump[w][q] = bsrc[q];
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            const uint32_t group = rfl(D.group);
-            const LdsDesc Dl = (LdsDesc)&wdesc[w];
-            switch (kind) {
-            case VRT_MEDIUM_HOMOGENEOUS: march_group<VRT_MEDIUM_HOMOGENEOUS>(c, Dl, B, group); break;
-            case VRT_MEDIUM_LINEAR: march_group<VRT_MEDIUM_LINEAR>(c, Dl, B, group); break;
-            case VRT_MEDIUM_LUNEBURG: march_group<VRT_MEDIUM_LUNEBURG>(c, Dl, B, group); break;
-            case VRT_MEDIUM_FIBER: march_group<VRT_MEDIUM_FIBER>(c, Dl, B, group); break;
-            case VRT_MEDIUM_GAUSSIAN: march_group<VRT_MEDIUM_GAUSSIAN>(c, Dl, B, group); break;
-            case VRT_MEDIUM_SPHERICAL: march_group<VRT_MEDIUM_SPHERICAL>(c, Dl, B, group); break;
-            case VRT_MEDIUM_N2P: march_group<VRT_MEDIUM_N2P>(c, Dl, B, group); break;
-            case VRT_MEDIUM_ZERNIKE: march_group<VRT_MEDIUM_ZERNIKE>(c, Dl, B, group); break;
-            default: march_group<VRT_MEDIUM_GRID>(c, Dl, B, group); break;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_dcache_inv();
+            const int kind = (int)rfl((uint32_t)table[sl].kind);
+            const uint32_t group = rfl(table[sl].group);
+            const ConstDesc Dc = (ConstDesc)mine;
+            if constexpr (kClass == 0) {
+                switch (kind) {
+                case VRT_MEDIUM_HOMOGENEOUS: march_group<VRT_MEDIUM_HOMOGENEOUS>(c, Dc, group); break;
+                case VRT_MEDIUM_LINEAR: march_group<VRT_MEDIUM_LINEAR>(c, Dc, group); break;
+                case VRT_MEDIUM_LUNEBURG: march_group<VRT_MEDIUM_LUNEBURG>(c, Dc, group); break;
+                case VRT_MEDIUM_FIBER: march_group<VRT_MEDIUM_FIBER>(c, Dc, group); break;
+                case VRT_MEDIUM_GAUSSIAN: march_group<VRT_MEDIUM_GAUSSIAN>(c, Dc, group); break;
+                case VRT_MEDIUM_SPHERICAL: march_group<VRT_MEDIUM_SPHERICAL>(c, Dc, group); break;
+                default: march_group<VRT_MEDIUM_N2P>(c, Dc, group); break;
+                }
+            } else {
+                if (kind == VRT_MEDIUM_ZERNIKE)
+                    march_group<VRT_MEDIUM_ZERNIKE>(c, Dc, group);
+                else
+                    march_group<VRT_MEDIUM_GRID>(c, Dc, group);
             }
             idle = 0;
             continue;
@@ -504,8 +539,8 @@ __global__ __launch_bounds__(256, kServeOcc) void serve_kernel(const JobDesc *hd
         if (idle > kIdlePolls && (idle % 8 == 0 || idle == kIdlePolls + 1)) {
             const bool stop =
                 __hip_atomic_load(&mb->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
-            const bool live =
-                __hip_atomic_load(&mb->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+            const bool live = __hip_atomic_load(&mb->live[kClass][0], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_SYSTEM) != 0;
             if (stop || !live || idle > kLingerPolls) {
                 if (c.lane == 0)
                     __hip_atomic_store(&dc->exiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -528,6 +563,7 @@ struct HostJob {
     size_t n = 0;
     size_t off = 0, bytes = 0;
     int state = VRT_JOB_QUEUED;
+    int cls = 0;  // medium class (which persistent kernel marches it)
     int error = 0;
     uint64_t steps = 0;
     double t_submit = 0, t_admit = 0, t_start = 0, t_retired = 0, t_done = 0;
@@ -599,6 +635,7 @@ struct vrt_server_s {
     Mailbox *mb = nullptr;     // pinned, coherent
     DoneRec *done = nullptr;   // pinned, coherent
     JobDesc *table = nullptr;  // device
+    JobDesc *wdg = nullptr;    // device: each wave's copy of its group descriptor
     JobCtl *ctl = nullptr;     // device
     DevCtl *dc = nullptr;      // device
     std::vector<char> slot_busy;
@@ -607,10 +644,13 @@ struct vrt_server_s {
     std::vector<hsa_signal_t> free_sigs;
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[kClasses] = {};
+    hipGraphExec_t exec[kClasses] = {};
     bool running = false;
-    uint32_t blocks = 0;
+    int run_cls = 0;         // class of the running (or last) kernel
+    double run_t0 = 0;       // when it was launched
+    bool yield_sent = false;
+    uint32_t blocks[kClasses] = {};
     uint32_t futile = 0;  // kernel runs since a job last retired
     std::mutex mu;
     std::condition_variable cv_submit, cv_done;
@@ -619,7 +659,8 @@ struct vrt_server_s {
     std::unordered_map<uint64_t, HostJob *> jobs;
     std::map<std::vector<uint64_t>, uint32_t> groups;  // (medium, trace parameters) -> group id
     uint32_t next_seq = 0;
-    uint32_t admitted = 0;  // admitted and not retired (the mailbox's live)
+    uint32_t admitted = 0;  // admitted and not retired
+    uint32_t admitted_cls[kClasses] = {};  // the same per class (the mailbox's live)
     uint32_t published = 0; // jobs [0, published) staged and announced
     bool quit = false;
     int fatal = 0;
@@ -753,7 +794,10 @@ static void finish_job(vrt_server_t s, HostJob *J, int err) {
     s->st.pool_bytes = s->alloc.used();
 }
 
-static void set_live(vrt_server_t s) { __atomic_store_n(&s->mb->live, s->admitted, __ATOMIC_RELEASE); }
+static void set_live(vrt_server_t s) {
+    for (int k = 0; k < kClasses; ++k)
+        __atomic_store_n(&s->mb->live[k][0], s->admitted_cls[k], __ATOMIC_RELEASE);
+}
 
 // One pass of the scheduler (mu held).  Returns true if anything moved.
 static bool schedule_once(vrt_server_t s) {
@@ -772,6 +816,7 @@ static bool schedule_once(vrt_server_t s) {
         J->t_admit = s->now();
         J->state = VRT_JOB_RUNNING;
         s->admitted++;
+        s->admitted_cls[J->cls]++;
         set_live(s);
         if (!stage_job(s, J)) {
             set_fatal(s, VRT_EHIP, "server: input copy could not be issued");
@@ -796,29 +841,42 @@ static bool schedule_once(vrt_server_t s) {
         s->live.push_back(J);
         moved = true;
     }
-    // 3. the persistent kernel runs while jobs are admitted
+    // 3. one persistent kernel at a time, of one medium class, runs while jobs
+    //    of its class are admitted; when both classes have jobs the classes
+    //    alternate, a run yielding after kSliceSec (its waves claim no more
+    //    rays, finish the ones they hold and leave)
     if (s->running) {
         e = hipEventQuery(s->ev);
         if (e == hipSuccess) {
             s->running = false;
         } else if (e != hipErrorNotReady) {
             goto fail;
+        } else if (!s->yield_sent && s->admitted_cls[s->run_cls ^ 1] > 0 &&
+                   s->now() - s->run_t0 > kSliceSec) {
+            __atomic_store_n(&s->mb->yield, 1u, __ATOMIC_RELEASE);
+            s->yield_sent = true;
         }
     }
     if (!s->running && s->admitted > 0) {
         // a run that retires nothing while jobs are live can only repeat: stop
-        if (++s->futile > 16) {
+        if (++s->futile > 64) {
             set_fatal(s, VRT_EHIP, "server: published jobs make no progress");
             return false;
         }
+        const int other = s->run_cls ^ 1;
+        const int cls = s->admitted_cls[other] > 0 ? other : s->run_cls;
         // the previous run has ended: clear its exit flag (no wave reads it now)
+        __atomic_store_n(&s->mb->yield, 0u, __ATOMIC_RELEASE);
         if ((e = hipMemsetAsync(&s->dc->exiting, 0, sizeof(uint32_t), s->stream)) != hipSuccess)
             goto fail;
-        if ((e = hipGraphLaunch(s->exec, s->stream)) != hipSuccess) goto fail;
+        if ((e = hipGraphLaunch(s->exec[cls], s->stream)) != hipSuccess) goto fail;
         if ((e = hipEventRecord(s->ev, s->stream)) != hipSuccess) goto fail;
         s->running = true;
+        s->run_cls = cls;
+        s->run_t0 = s->now();
+        s->yield_sent = false;
         s->st.kernel_launches++;
-        s->st.lanes = s->blocks * 256;
+        s->st.lanes = s->blocks[cls] * 256;
         moved = true;
     }
     if (__atomic_load_n(&s->mb->lost, __ATOMIC_ACQUIRE)) {
@@ -835,6 +893,7 @@ static bool schedule_once(vrt_server_t s) {
             J->state = VRT_JOB_COPYING;
             s->futile = 0;
             s->admitted--;
+            s->admitted_cls[J->cls]--;
             set_live(s);
             if (!fetch_job(s, J)) {
                 set_fatal(s, VRT_EHIP, "server: output copy could not be issued");
@@ -934,13 +993,16 @@ static int server_free(vrt_server_t s) {
     if (s->hsa_up) drain_signals(s);
     for (auto &sg : s->free_sigs) (void)hsa_signal_destroy(sg);
     s->free_sigs.clear();
-    if (s->exec) (void)hipGraphExecDestroy(s->exec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
+    for (int k = 0; k < kClasses; ++k) {
+        if (s->exec[k]) (void)hipGraphExecDestroy(s->exec[k]);
+        if (s->graph[k]) (void)hipGraphDestroy(s->graph[k]);
+    }
     if (s->ev) (void)hipEventDestroy(s->ev);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     for (auto &kv : s->jobs) delete kv.second;
     if (s->pool) (void)hipFree(s->pool);
     if (s->table) (void)hipFree(s->table);
+    if (s->wdg) (void)hipFree(s->wdg);
     if (s->ctl) (void)hipFree(s->ctl);
     if (s->dc) (void)hipFree(s->dc);
     if (s->hdesc) (void)hipHostFree(s->hdesc);
@@ -1004,6 +1066,8 @@ extern "C" int vrt_server_create(vrt_context_t ctx, size_t hbm_budget, int max_l
     } while (0)
     SV_TRY(hipMalloc((void **)&s->pool, s->budget), "pool");
     SV_TRY(hipMalloc((void **)&s->table, sizeof(JobDesc) * kSlots), "job table");
+    SV_TRY(hipMalloc((void **)&s->wdg, sizeof(JobDesc) * 4 * (size_t)ctx->num_cu * kMaxBlocksPerCu),
+           "wave descriptors");
     SV_TRY(hipMalloc((void **)&s->ctl, sizeof(JobCtl) * kSlots), "job counters");
     SV_TRY(hipMalloc((void **)&s->dc, sizeof(DevCtl)), "control words");
     SV_TRY(hipHostMalloc((void **)&s->hdesc, sizeof(JobDesc) * kSlots, hipHostMallocCoherent),
@@ -1029,16 +1093,24 @@ extern "C" int vrt_server_create(vrt_context_t ctx, size_t hbm_budget, int max_l
         SV_TRY(hipMemset(s->table, 0, sizeof(JobDesc) * kSlots), "table init");
         SV_TRY(hipMemset(s->dc, 0, sizeof(DevCtl)), "control init");
     }
-    int occ = 0;
-    SV_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, serve_kernel, 256, 0), "occupancy");
-    occ = std::max(occ, 1);
-    s->blocks = (uint32_t)ctx->num_cu * (uint32_t)occ;
-    if (max_lanes > 0) s->blocks = std::min(s->blocks, std::max(1u, (uint32_t)max_lanes / 256u));
-    SV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal), "capture");
-    hipLaunchKernelGGL(serve_kernel, dim3(s->blocks), dim3(256), 0, s->stream, s->hdesc, s->table,
-                       s->ctl, s->dc, s->mb, s->done);
-    SV_TRY(hipStreamEndCapture(s->stream, &s->graph), "capture");
-    SV_TRY(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0), "graph");
+    for (int k = 0; k < kClasses; ++k) {
+        const void *fn = k == 0 ? (const void *)serve_kernel<0> : (const void *)serve_kernel<1>;
+        int occ = 0;
+        SV_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, 0), "occupancy");
+        occ = std::min(std::max(occ, 1), kMaxBlocksPerCu);
+        s->blocks[k] = (uint32_t)ctx->num_cu * (uint32_t)occ;
+        if (max_lanes > 0)
+            s->blocks[k] = std::min(s->blocks[k], std::max(1u, (uint32_t)max_lanes / 256u));
+        SV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal), "capture");
+        if (k == 0)
+            hipLaunchKernelGGL(serve_kernel<0>, dim3(s->blocks[k]), dim3(256), 0, s->stream,
+                               s->hdesc, s->table, s->ctl, s->dc, s->mb, s->done, s->wdg);
+        else
+            hipLaunchKernelGGL(serve_kernel<1>, dim3(s->blocks[k]), dim3(256), 0, s->stream,
+                               s->hdesc, s->table, s->ctl, s->dc, s->mb, s->done, s->wdg);
+        SV_TRY(hipStreamEndCapture(s->stream, &s->graph[k]), "capture");
+        SV_TRY(hipGraphInstantiate(&s->exec[k], s->graph[k], nullptr, nullptr, 0), "graph");
+    }
     s->st.job_slots = kSlots;
 #undef SV_TRY
 #undef SV_FAIL
@@ -1083,6 +1155,7 @@ extern "C" int vrt_server_submit(vrt_server_t s, vrt_medium_t m, const vrt_trace
                     n_rays, bytes, s->budget);
     HostJob *J = new HostJob();
     J->med = m;
+    J->cls = medium_class(m->dev.kind);
     J->p = *p;
     J->host = *host_rays;
     J->n = n_rays;
