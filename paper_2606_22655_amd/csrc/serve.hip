@@ -1,7 +1,10 @@
-// serve.hip -- continuous batching of trace jobs: one persistent kernel
-// marches the rays of every admitted job, of every medium kind, while a host
+// serve.hip -- continuous batching of trace jobs: a persistent kernel marches
+// the rays of every admitted job of one medium kind at a time, while a host
 // thread admits new jobs into a device pool of fixed size, hands them to the
-// running kernel and copies finished jobs back.
+// running kernel and copies finished jobs back.  Each medium kind has its own
+// persistent kernel (the batch kernel's march of that kind, compiled for the
+// occupancy its registers allow); when jobs of several kinds are admitted the
+// kinds take turns, a run yielding after kSliceSec.
 //
 // The running kernel never waits for anything queued on a stream: a
 // persistent kernel can hold the hardware queue (and the compute units) that
@@ -30,9 +33,9 @@
 // fresh.
 //
 // A wave works on one group at a time -- the jobs with the same medium and
-// trace parameters -- whose descriptor and Gaussian bump table it copies into
-// LDS, so the medium is uniform across its lanes and its constants are LDS
-// reads; the march of the group's medium kind is selected once per group.
+// trace parameters -- whose descriptor it copies to a slot of its own and then
+// reads, with the medium's Gaussian bump table, as constants through the
+// scalar cache (as the batch kernel reads its kernel arguments).
 // Its idle lanes claim rays, in job order, from the group's jobs with one
 // fetch-and-add per job on the claim word, whose sequence bits confirm that
 // the slot still held the job; a lane's ray keeps its own job (inputs,
@@ -83,15 +86,16 @@ constexpr uint32_t kFlushEvery = 256;   // iterations between accounting flushes
 constexpr int kMaxBlocksPerCu = 4;      // wave descriptor copies are sized for this
 constexpr double kSliceSec = 0.025;     // a class's run yields after this when the other waits
 
-// Medium classes, one persistent kernel each: the marches of a class share a
-// register budget, so each class runs at the occupancy its heaviest march
-// allows (analytic media at 3 blocks per CU like the batch kernel; grids and
-// the Zernike lens, whose marches need ~215 VGPRs, at 2).
-constexpr int kClasses = 2;
-__host__ __device__ constexpr int medium_class(int kind) {
-    return kind == VRT_MEDIUM_GRID || kind == VRT_MEDIUM_ZERNIKE ? 1 : 0;
+// One persistent kernel per medium kind: each is the batch kernel's march of
+// its kind wrapped in the job claiming and accounting, compiled for the
+// occupancy its registers allow (analytic media at 3 blocks per CU, grids and
+// the Zernike lens, whose marches need ~215 VGPRs, at 2).  One kind's kernel is
+// resident at a time; the kinds with admitted jobs take turns.
+constexpr int kClasses = VRT_MEDIUM_ZERNIKE + 1;
+__host__ __device__ constexpr int medium_class(int kind) { return kind; }
+__host__ __device__ constexpr int class_occupancy(int kind) {
+    return kind == VRT_MEDIUM_GRID || kind == VRT_MEDIUM_ZERNIKE ? 2 : 3;
 }
-__host__ __device__ constexpr int class_occupancy(int cls) { return cls == 0 ? 3 : 2; }
 
 struct alignas(16) JobDesc {
     MediumDev m;
@@ -305,8 +309,7 @@ __device__ __forceinline__ bool claimable(const WaveCtx &c, uint32_t jj, int cls
 // per medium kind, not inlined: each gets the registers of its own march
 // (inlined side by side, the kinds' marches spill).
 template <int MK>
-__device__ __attribute__((noinline)) void march_group(WaveCtx &cw, ConstDesc Dp,
-                                                      uint32_t group_in) {
+__device__ __forceinline__ void march_group(WaveCtx &cw, ConstDesc Dp, uint32_t group_in) {
     WaveCtx c;  // wave-uniform copies in scalar registers
     c.hdesc = rfl_ptr(cw.hdesc);
     c.table = rfl_ptr(cw.table);
@@ -512,25 +515,9 @@ __global__ __launch_bounds__(256, class_occupancy(kClass)) void serve_kernel(
             for (uint32_t q = c.lane; q < sizeof(JobDesc) / 16; q += 64) dst[q] = src[q];
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __builtin_amdgcn_s_dcache_inv();
-            const int kind = (int)rfl((uint32_t)table[sl].kind);
             const uint32_t group = rfl(table[sl].group);
             const ConstDesc Dc = (ConstDesc)mine;
-            if constexpr (kClass == 0) {
-                switch (kind) {
-                case VRT_MEDIUM_HOMOGENEOUS: march_group<VRT_MEDIUM_HOMOGENEOUS>(c, Dc, group); break;
-                case VRT_MEDIUM_LINEAR: march_group<VRT_MEDIUM_LINEAR>(c, Dc, group); break;
-                case VRT_MEDIUM_LUNEBURG: march_group<VRT_MEDIUM_LUNEBURG>(c, Dc, group); break;
-                case VRT_MEDIUM_FIBER: march_group<VRT_MEDIUM_FIBER>(c, Dc, group); break;
-                case VRT_MEDIUM_GAUSSIAN: march_group<VRT_MEDIUM_GAUSSIAN>(c, Dc, group); break;
-                case VRT_MEDIUM_SPHERICAL: march_group<VRT_MEDIUM_SPHERICAL>(c, Dc, group); break;
-                default: march_group<VRT_MEDIUM_N2P>(c, Dc, group); break;
-                }
-            } else {
-                if (kind == VRT_MEDIUM_ZERNIKE)
-                    march_group<VRT_MEDIUM_ZERNIKE>(c, Dc, group);
-                else
-                    march_group<VRT_MEDIUM_GRID>(c, Dc, group);
-            }
+            march_group<kClass>(c, Dc, group);
             idle = 0;
             continue;
         }
@@ -851,7 +838,7 @@ static bool schedule_once(vrt_server_t s) {
             s->running = false;
         } else if (e != hipErrorNotReady) {
             goto fail;
-        } else if (!s->yield_sent && s->admitted_cls[s->run_cls ^ 1] > 0 &&
+        } else if (!s->yield_sent && s->admitted > s->admitted_cls[s->run_cls] &&
                    s->now() - s->run_t0 > kSliceSec) {
             __atomic_store_n(&s->mb->yield, 1u, __ATOMIC_RELEASE);
             s->yield_sent = true;
@@ -863,8 +850,15 @@ static bool schedule_once(vrt_server_t s) {
             set_fatal(s, VRT_EHIP, "server: published jobs make no progress");
             return false;
         }
-        const int other = s->run_cls ^ 1;
-        const int cls = s->admitted_cls[other] > 0 ? other : s->run_cls;
+        // the next kind after the last one run that has admitted jobs
+        int cls = s->run_cls;
+        for (int k = 1; k <= kClasses; ++k) {
+            const int q = (s->run_cls + k) % kClasses;
+            if (s->admitted_cls[q] > 0) {
+                cls = q;
+                break;
+            }
+        }
         // the previous run has ended: clear its exit flag (no wave reads it now)
         __atomic_store_n(&s->mb->yield, 0u, __ATOMIC_RELEASE);
         if ((e = hipMemsetAsync(&s->dc->exiting, 0, sizeof(uint32_t), s->stream)) != hipSuccess)
@@ -1093,8 +1087,12 @@ extern "C" int vrt_server_create(vrt_context_t ctx, size_t hbm_budget, int max_l
         SV_TRY(hipMemset(s->table, 0, sizeof(JobDesc) * kSlots), "table init");
         SV_TRY(hipMemset(s->dc, 0, sizeof(DevCtl)), "control init");
     }
+    const void *fns[kClasses] = {
+        (const void *)serve_kernel<0>, (const void *)serve_kernel<1>, (const void *)serve_kernel<2>,
+        (const void *)serve_kernel<3>, (const void *)serve_kernel<4>, (const void *)serve_kernel<5>,
+        (const void *)serve_kernel<6>, (const void *)serve_kernel<7>, (const void *)serve_kernel<8>};
     for (int k = 0; k < kClasses; ++k) {
-        const void *fn = k == 0 ? (const void *)serve_kernel<0> : (const void *)serve_kernel<1>;
+        const void *fn = fns[k];
         int occ = 0;
         SV_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, 0), "occupancy");
         occ = std::min(std::max(occ, 1), kMaxBlocksPerCu);
@@ -1102,12 +1100,8 @@ extern "C" int vrt_server_create(vrt_context_t ctx, size_t hbm_budget, int max_l
         if (max_lanes > 0)
             s->blocks[k] = std::min(s->blocks[k], std::max(1u, (uint32_t)max_lanes / 256u));
         SV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal), "capture");
-        if (k == 0)
-            hipLaunchKernelGGL(serve_kernel<0>, dim3(s->blocks[k]), dim3(256), 0, s->stream,
-                               s->hdesc, s->table, s->ctl, s->dc, s->mb, s->done, s->wdg);
-        else
-            hipLaunchKernelGGL(serve_kernel<1>, dim3(s->blocks[k]), dim3(256), 0, s->stream,
-                               s->hdesc, s->table, s->ctl, s->dc, s->mb, s->done, s->wdg);
+        void *args[] = {&s->hdesc, &s->table, &s->ctl, &s->dc, &s->mb, &s->done, &s->wdg};
+        SV_TRY(hipLaunchKernel(fn, dim3(s->blocks[k]), dim3(256), args, 0, s->stream), "launch");
         SV_TRY(hipStreamEndCapture(s->stream, &s->graph[k]), "capture");
         SV_TRY(hipGraphInstantiate(&s->exec[k], s->graph[k], nullptr, nullptr, 0), "graph");
     }
