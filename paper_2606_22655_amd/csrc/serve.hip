@@ -781,6 +781,14 @@ static void finish_job(vrt_server_t s, HostJob *J, int err) {
     s->st.pool_bytes = s->alloc.used();
 }
 
+// Medium kind of the oldest published job that has not retired (-1: none).
+static int oldest_kind(vrt_server_t s) {
+    const HostJob *o = nullptr;
+    for (const HostJob *J : s->live)
+        if (!o || J->seq < o->seq) o = J;
+    return o ? o->cls : -1;
+}
+
 static void set_live(vrt_server_t s) {
     for (int k = 0; k < kClasses; ++k)
         __atomic_store_n(&s->mb->live[k][0], s->admitted_cls[k], __ATOMIC_RELEASE);
@@ -828,37 +836,31 @@ static bool schedule_once(vrt_server_t s) {
         s->live.push_back(J);
         moved = true;
     }
-    // 3. one persistent kernel at a time, of one medium class, runs while jobs
-    //    of its class are admitted; when both classes have jobs the classes
-    //    alternate, a run yielding after kSliceSec (its waves claim no more
-    //    rays, finish the ones they hold and leave)
+    // 3. one persistent kernel at a time, of one medium kind, runs while jobs
+    //    of its kind are admitted.  Jobs are served oldest first, as the waves
+    //    of one kernel take them: the kernel run is of the oldest admitted
+    //    job's kind, and a run yields (its waves claim no more rays, finish the
+    //    ones they hold and leave) once it has run kSliceSec while the oldest
+    //    admitted job is of another kind.
     if (s->running) {
         e = hipEventQuery(s->ev);
         if (e == hipSuccess) {
             s->running = false;
         } else if (e != hipErrorNotReady) {
             goto fail;
-        } else if (!s->yield_sent && s->admitted > s->admitted_cls[s->run_cls] &&
-                   s->now() - s->run_t0 > kSliceSec) {
+        } else if (!s->yield_sent && s->now() - s->run_t0 > kSliceSec &&
+                   oldest_kind(s) != s->run_cls) {
             __atomic_store_n(&s->mb->yield, 1u, __ATOMIC_RELEASE);
             s->yield_sent = true;
         }
     }
-    if (!s->running && s->admitted > 0) {
+    if (!s->running && !s->live.empty()) {
         // a run that retires nothing while jobs are live can only repeat: stop
         if (++s->futile > 64) {
             set_fatal(s, VRT_EHIP, "server: published jobs make no progress");
             return false;
         }
-        // the next kind after the last one run that has admitted jobs
-        int cls = s->run_cls;
-        for (int k = 1; k <= kClasses; ++k) {
-            const int q = (s->run_cls + k) % kClasses;
-            if (s->admitted_cls[q] > 0) {
-                cls = q;
-                break;
-            }
-        }
+        const int cls = oldest_kind(s);
         // the previous run has ended: clear its exit flag (no wave reads it now)
         __atomic_store_n(&s->mb->yield, 0u, __ATOMIC_RELEASE);
         if ((e = hipMemsetAsync(&s->dc->exiting, 0, sizeof(uint32_t), s->stream)) != hipSuccess)
