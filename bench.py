@@ -267,7 +267,7 @@ def job_buffers(vrt, torch, pool, off, n):
     return r, (out, u32)
 
 
-def served_parity(vrt, torch, jobs, keep, pools, meds, media, prm, offset, n_jobs=16,
+def served_parity(vrt, torch, jobs, keep, pools, meds, media, prm, offset, pick,
                   n_oracle=256):
     """Parity of the served results: for a seeded sample of jobs, every ray of
     the job against a vrt_trace batch launch of the same rays (bitwise: the
@@ -280,8 +280,7 @@ def served_parity(vrt, torch, jobs, keep, pools, meds, media, prm, offset, n_job
     sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
     from parity import compare
 
-    rng = np.random.default_rng(77)
-    pick = np.sort(rng.choice(len(jobs), min(n_jobs, len(jobs)), replace=False))
+    rng = np.random.default_rng(78)
     rep = {"jobs": len(pick), "rays_bitwise_checked": 0, "rays_bitwise_differ": 0,
            "oracle_rays": 0, "oracle_fail": 0, "oracle_exempt_critical": 0,
            "oracle_exempt_grazing": 0, "oracle_pos_err_max": 0.0, "oracle_dir_err_max": 0.0}
@@ -359,21 +358,41 @@ def served_bench(vrt, torch, args):
     def offset(j):
         return j["ray_seed"] % (POOL_RAYS - j["n_rays"] + 1)
 
-    # served run: submit at the arrival times
-    keep, ids = [], []
+    # served run: submit at the arrival times; a job's pinned buffers are
+    # released once it is done, except those of the jobs whose results the
+    # parity block checks
+    sample = set(np.sort(np.random.default_rng(77).choice(len(jobs), min(16, len(jobs)),
+                                                          replace=False)).tolist())
+    keep, ids, infos, pending = {}, [], [None] * len(jobs), []
     t_base = time.perf_counter()
+    every = 10 if len(jobs) <= 1000 else 100
+
+    def reap(block=False):
+        while pending:
+            k = pending[0]
+            info = (vrt.vrt_server_wait(srv.handle, ids[k], 600.0) if block else
+                    vrt.vrt_server_query(srv.handle, ids[k]))
+            if info["state"] != "DONE":
+                return
+            infos[k] = info
+            pending.pop(0)
+            if k not in sample:
+                keep.pop(k, None)
+
     for k, j in enumerate(jobs):
         wait = j["t_arrival"] - (time.perf_counter() - t_base)
         if wait > 0:
             time.sleep(wait)
-        if k % 10 == 0:
+        if k % every == 0:
             print(f"[served] submitting job {k} at {time.perf_counter() - t_base:.2f} s",
                   file=sys.stderr, flush=True)
         r, bufs = job_buffers(vrt, torch, pools[j["medium"]], offset(j), j["n_rays"])
-        keep.append(bufs)
+        keep[k] = bufs
         ids.append(vrt.vrt_server_submit(srv.handle, meds[j["medium"]].handle,
                                          vrt.make_params(prm, "fp32c"), r, j["n_rays"]))
-    infos = [vrt.vrt_server_wait(srv.handle, jid, 600.0) for jid in ids]
+        pending.append(k)
+        reap()
+    reap(block=True)
     stats = vrt.vrt_server_stats_get(srv.handle)
     srv.close()
     lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
@@ -387,13 +406,17 @@ def served_bench(vrt, torch, args):
               "pool_peak_bytes": stats["pool_peak_bytes"], "lanes": stats["lanes"]}
     print(f"[served] fp32c: {rays / span:.4g} rays/s, p50 {served['p50_ms']:.1f} ms, "
           f"p99 {served['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
-    served["parity"] = served_parity(vrt, torch, jobs, keep, pools, meds, media, prm, offset)
+    served["parity"] = served_parity(vrt, torch, jobs, keep, pools, meds, media, prm, offset,
+                                     sorted(sample))
     del keep
-    # the same stream, one FP64 launch per job, FIFO on one stream
+    # the same stream (or its first fp64_jobs jobs), one FP64 launch per job,
+    # FIFO on one stream
     stream = torch.cuda.current_stream()
     lat64, busy = [], 0.0
     clock = 0.0  # simulated clock on the arrival axis: a job starts at max(arrival, previous end)
-    for k, j in enumerate(jobs):
+    n64 = len(jobs) if args.fp64_jobs is None else min(args.fp64_jobs, len(jobs))
+    rays64 = sum(j["n_rays"] for j in jobs[:n64])
+    for k, j in enumerate(jobs[:n64]):
         if k % 10 == 0:
             print(f"[served] fp64 job {k}", file=sys.stderr, flush=True)
         n, src = j["n_rays"], pools[j["medium"]]
@@ -408,12 +431,13 @@ def served_bench(vrt, torch, args):
         lat64.append(clock - j["t_arrival"])
         del b
     lat64 = np.array(lat64)
-    fp64 = {"rays_per_s": rays / busy, "p50_ms": 1e3 * float(np.percentile(lat64, 50)),
+    fp64 = {"jobs": n64, "rays_per_s": rays64 / busy,
+            "p50_ms": 1e3 * float(np.percentile(lat64, 50)),
             "p99_ms": 1e3 * float(np.percentile(lat64, 99)), "busy_s": busy,
             "note": "jobs run back to back on the GPU, one FP64 launch each (inputs copied in, "
                     "outputs copied out); each job starts at max(its arrival, the previous "
                     "job's end) on the arrival clock"}
-    print(f"[served] fp64 per job: {rays / busy:.4g} rays/s, p50 {fp64['p50_ms']:.1f} ms, "
+    print(f"[served] fp64 per job ({n64} jobs): {rays64 / busy:.4g} rays/s, p50 {fp64['p50_ms']:.1f} ms, "
           f"p99 {fp64['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
     for m in meds:
         m.close()
@@ -824,6 +848,8 @@ def main(argv=None):
                     choices=["headline", "freeform", "grid", "luneburg", "zernike", "spherical",
                              "helix", "served", "n2p", "adjoint"])
     ap.add_argument("--jobs", type=int, default=120, help="served: jobs in the arrival stream")
+    ap.add_argument("--fp64-jobs", type=int, default=None,
+                    help="served: run the one-launch-per-job FP64 baseline on this prefix")
     ap.add_argument("--load", type=float, default=0.8,
                     help="served: offered load as a fraction of the measured capacity")
     ap.add_argument("--rays", type=int, default=None)
