@@ -319,8 +319,9 @@ constexpr bool kIndexIn64 =
 // at P_i where the medium's constant part is split off (homogeneous, linear,
 // Gaussian: n0 exactly as given plus the float-summed variable part); nl = 0
 // for the Luneburg and fiber media.  bumps: the Gaussian
-// table (m.bumps_f) -- a restrict kernel argument in the batch kernel (its
-// loads are then scalar), a copy in LDS in the serving kernel.
+// table (m.bumps_f) -- a restrict kernel argument in the batch kernel, a
+// constant-address-space pointer in the serving kernel; its loads are scalar
+// in both.
 // MedF.q: HOMOGENEOUS [n, n - (float)n]; LINEAR [n0, gx, gy, gz, n0 - (float)n0];
 // LUNEBURG [., cx, cy, cz, 1/R^2]; FIBER [n_c, Delta, ., cx, cy, 2 Delta n_c^2/R^2,
 // n_clad, R^2]; GAUSSIAN [n0, largest dL0 for the degree-3 difference form,
