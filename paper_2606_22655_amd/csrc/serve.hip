@@ -82,7 +82,7 @@ constexpr uint32_t kDryEvery = 1024;
 constexpr uint64_t kPollTicks = 200;    // 2 us at the 100 MHz wall clock between host-tail polls
 constexpr int kRanges = 4;              // job ranges one refill may draw from
 constexpr uint32_t kScan = 64;          // jobs a refill looks ahead for its group
-constexpr uint32_t kFlushEvery = 256;   // iterations between accounting flushes
+constexpr uint32_t kFlushEvery = 256;   // refill iterations between accounting flushes
 constexpr int kMaxBlocksPerCu = 4;      // wave descriptor copies are sized for this
 constexpr double kSliceSec = 0.025;     // a class's run yields after this when the other waits
 
@@ -145,13 +145,6 @@ struct DoneRec {
 };
 
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-template <class T>
-__device__ __forceinline__ T *rfl_ptr(T *p) {
-    const uint64_t v = (uint64_t)p;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (T *)(((uint64_t)hi << 32) | lo);
-}
 
 // The wave's group descriptor and bump table are read through the scalar
 // data cache, as kernel arguments are: pointers in the constant address space
@@ -166,14 +159,23 @@ __device__ __forceinline__ P rfl_cptr(P p) {
     return (P)(((uint64_t)hi << 32) | lo);
 }
 
-// Pointers and wave-uniform progress of one wave.
-struct WaveCtx {
+// The server's arrays, passed as the kernel's one argument and read through
+// a pointer to it: like the batch kernel's launch descriptor, its fields live
+// in constant memory and are loaded where used, not held in scalar registers
+// across the march.
+struct SrvPtrs {
     const JobDesc *hdesc;
     JobDesc *table;
     JobCtl *ctl;
     DevCtl *dc;
     Mailbox *mb;
     DoneRec *done;
+    JobDesc *wdg;  // each wave's copy of its group descriptor
+};
+
+// Pointers and wave-uniform progress of one wave.
+struct WaveCtx {
+    const SrvPtrs *__restrict__ P;
     unsigned long long *wacc;  // two LDS words of the wave
     int lane;
     uint32_t jcur;  // no job below it has rays for this wave
@@ -189,10 +191,10 @@ __device__ __forceinline__ void maybe_activate(WaveCtx &c) {
     uint32_t go = 0;
     if (c.lane == 0) {
         const unsigned long long last =
-            __hip_atomic_load(&c.dc->poll_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_load(&c.P->dc->poll_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (now - last >= kPollTicks) {
             uint32_t z = 0;
-            go = __hip_atomic_compare_exchange_strong(&c.dc->act, &z, 1u, __ATOMIC_ACQUIRE,
+            go = __hip_atomic_compare_exchange_strong(&c.P->dc->act, &z, 1u, __ATOMIC_ACQUIRE,
                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                      ? 1u
                      : 0u;
@@ -200,37 +202,37 @@ __device__ __forceinline__ void maybe_activate(WaveCtx &c) {
     }
     if (!rfl(__shfl(go, 0))) return;
     if (c.lane == 0 &&
-        __hip_atomic_load(&c.mb->yield, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
-        __hip_atomic_store(&c.dc->exiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_load(&c.P->mb->yield, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+        __hip_atomic_store(&c.P->dc->exiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t ht =
-        rfl(__hip_atomic_load(&c.mb->htail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
+        rfl(__hip_atomic_load(&c.P->mb->htail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
     const uint32_t dt =
-        rfl(__hip_atomic_load(&c.dc->dtail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        rfl(__hip_atomic_load(&c.P->dc->dtail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     for (uint32_t j = dt; j < ht; ++j) {
         const uint32_t sl = j % kSlots;
-        const uint4 *src = (const uint4 *)(c.hdesc + sl);
-        uint4 *dst = (uint4 *)(c.table + sl);
+        const uint4 *src = (const uint4 *)(c.P->hdesc + sl);
+        uint4 *dst = (uint4 *)(c.P->table + sl);
         for (uint32_t q = c.lane; q < sizeof(JobDesc) / 16; q += 64) dst[q] = src[q];
         if (c.lane == 0) {
-            __hip_atomic_store(&c.ctl[sl].steps, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&c.ctl[sl].left, c.hdesc[sl].n, __ATOMIC_RELAXED,
+            __hip_atomic_store(&c.P->ctl[sl].steps, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c.P->ctl[sl].left, c.P->hdesc[sl].n, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&c.ctl[sl].claim, (unsigned long long)j << 32, __ATOMIC_RELAXED,
+            __hip_atomic_store(&c.P->ctl[sl].claim, (unsigned long long)j << 32, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // descriptors and counts before dtail
     if (c.lane == 0) {
-        if (ht > dt) __hip_atomic_store(&c.dc->dtail, ht, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&c.dc->poll_t, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&c.dc->act, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (ht > dt) __hip_atomic_store(&c.P->dc->dtail, ht, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&c.P->dc->poll_t, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&c.P->dc->act, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 // Take up jobs activated since the wave last looked.  Returns true if any.
 __device__ __forceinline__ bool refresh_tail(WaveCtx &c) {
     const uint32_t dt =
-        rfl(__hip_atomic_load(&c.dc->dtail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        rfl(__hip_atomic_load(&c.P->dc->dtail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if (dt <= c.seen) return false;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // system scope: fresh descriptors and inputs
     c.seen = dt;
@@ -238,7 +240,7 @@ __device__ __forceinline__ bool refresh_tail(WaveCtx &c) {
 }
 
 __device__ __forceinline__ bool exiting(const WaveCtx &c) {
-    return __hip_atomic_load(&c.dc->exiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    return __hip_atomic_load(&c.P->dc->exiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
 // Account the wave's retired rays: one release at system scope (the outputs
@@ -268,7 +270,7 @@ __device__ __forceinline__ void flush_acc(WaveCtx &c, uint32_t aslot, uint32_t &
         __builtin_amdgcn_wave_barrier();
         if (c.lane == first) {
             const uint32_t cnt = (uint32_t)c.wacc[0];
-            JobCtl *jc = c.ctl + s0;
+            JobCtl *jc = c.P->ctl + s0;
             __hip_atomic_fetch_add(&jc->steps, c.wacc[1], __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t old =
@@ -279,9 +281,9 @@ __device__ __forceinline__ void flush_acc(WaveCtx &c, uint32_t aslot, uint32_t &
                     __hip_atomic_load(&jc->steps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t seq = (uint32_t)(
                     __hip_atomic_load(&jc->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32);
-                __hip_atomic_store(&c.done[s0].steps, st, __ATOMIC_RELAXED,
+                __hip_atomic_store(&c.P->done[s0].steps, st, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_SYSTEM);
-                __hip_atomic_store(&c.done[s0].seq1, seq + 1, __ATOMIC_RELEASE,
+                __hip_atomic_store(&c.P->done[s0].seq1, seq + 1, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }
@@ -298,9 +300,9 @@ __device__ __forceinline__ void flush_acc(WaveCtx &c, uint32_t aslot, uint32_t &
 __device__ __forceinline__ bool claimable(const WaveCtx &c, uint32_t jj, int cls) {
     const uint32_t sl = jj % kSlots;
     const unsigned long long w =
-        __hip_atomic_load(&c.ctl[sl].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return (uint32_t)(w >> 32) == jj && (uint32_t)w < c.table[sl].n &&
-           medium_class(c.table[sl].kind) == cls;
+        __hip_atomic_load(&c.P->ctl[sl].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (uint32_t)(w >> 32) == jj && (uint32_t)w < c.P->table[sl].n &&
+           medium_class(c.P->table[sl].kind) == cls;
 }
 
 // March rays of the wave's group (its descriptor copy and the medium's bump
@@ -311,12 +313,7 @@ __device__ __forceinline__ bool claimable(const WaveCtx &c, uint32_t jj, int cls
 template <int MK>
 __device__ __forceinline__ void march_group(WaveCtx &cw, ConstDesc Dp, uint32_t group_in) {
     WaveCtx c;  // wave-uniform copies in scalar registers
-    c.hdesc = rfl_ptr(cw.hdesc);
-    c.table = rfl_ptr(cw.table);
-    c.ctl = rfl_ptr(cw.ctl);
-    c.dc = rfl_ptr(cw.dc);
-    c.mb = rfl_ptr(cw.mb);
-    c.done = rfl_ptr(cw.done);
+    c.P = cw.P;
     c.wacc = cw.wacc;
     c.lane = __lane_id();
     c.jcur = rfl(cw.jcur);
@@ -337,151 +334,159 @@ __device__ __forceinline__ void march_group(WaveCtx &cw, ConstDesc Dp, uint32_t 
     unsigned long long asteps = 0;
     bool dry = false;  // the group had fewer rays than idle lanes at the last claim
     uint32_t dry_it = 0;
+    // The loop has the batch kernel's shape: an iteration in which every lane
+    // holds a ray only steps; claims, accounting and activation polls happen
+    // in iterations that find idle lanes (a ray ends every ~50 iterations of
+    // a wave, so they stay frequent).
     for (;;) {
         const uint64_t nm = ~act;  // lanes without a ray
-        bool fresh = false, claimed = false;
-        // The tail and claim words are contended addresses: a wave whose group
-        // ran dry looks for new jobs only every kDryEvery iterations.
-        if (nm && dry && ++dry_it % kDryEvery == 0) {
-            maybe_activate(c);
-            if (refresh_tail(c) && !exiting(c)) dry = false;
-        }
-        if (nm && !dry) {
-            const uint32_t want = (uint32_t)__popcll(nm);
-            const int leader = __ffsll((unsigned long long)nm) - 1;
-            // the wave marches a ray of job jcur: that job is not done, so its
-            // slot still holds it, and it is of the wave's group
-            const bool hold = __ballot(active && lslot == c.jcur % kSlots) != 0;
-            uint32_t r0 = 0, b0 = 0, c0 = 0, r1 = 0, b1 = 0, c1 = 0, r2 = 0, b2 = 0, c2 = 0,
-                     r3 = 0, b3 = 0, c3 = 0, nr = 0, jc = c.jcur, unmet = 0;
-            if (c.lane == leader) {
-                // claim, in job order, from the jobs of the wave's group
-                uint32_t need = exiting(c) ? 0u : want;
-                unmet = need == 0;
-                const uint32_t lim = min(c.seen, c.jcur + kScan);
-                for (uint32_t jj = c.jcur; need && jj < lim && nr < (uint32_t)kRanges; ++jj) {
-                    const uint32_t sl = jj % kSlots;
-                    const uint32_t nj = c.table[sl].n;
-                    const bool held = hold && jj == c.jcur;
-                    bool gone = false;
-                    if (!held) {
-                        const unsigned long long w = __hip_atomic_load(
-                            &c.ctl[sl].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        gone = (uint32_t)(w >> 32) != jj || (uint32_t)w >= nj;
-                    }
-                    if (!gone && (held || c.table[sl].group == group)) {
-                        // one fetch-and-add (a compare-and-swap loop here stalls every
-                        // wave on one contended word); an add past the end only takes
-                        // what is left, and n < 2^31 keeps the overshoot out of the
-                        // sequence bits.
-                        const unsigned long long o = __hip_atomic_fetch_add(
-                            &c.ctl[sl].claim, (unsigned long long)need, __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT);
-                        const uint32_t cn = (uint32_t)o;
-                        if ((uint32_t)(o >> 32) != jj) {
-                            // the slot was reused between the check and the add: the
-                            // new job lost rays it can never get back -- report it
-                            __hip_atomic_store(&c.mb->lost, 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_SYSTEM);
-                            gone = true;
-                        } else if (cn >= nj) {
-                            gone = true;
-                        } else {
-                            const uint32_t take = min(need, nj - cn);
-                            if (nr == 0) { r0 = sl; b0 = cn; c0 = take; }
-                            else if (nr == 1) { r1 = sl; b1 = cn; c1 = take; }
-                            else if (nr == 2) { r2 = sl; b2 = cn; c2 = take; }
-                            else { r3 = sl; b3 = cn; c3 = take; }
-                            ++nr;
-                            need -= take;
-                            gone = cn + take >= nj;
+        if (nm) {
+            bool fresh = false, claimed = false;
+            ++c.it;
+            // The tail and claim words are contended addresses: a wave whose
+            // group ran dry looks for new jobs only every kDryEvery iterations.
+            if (dry && ++dry_it % kDryEvery == 0) {
+                maybe_activate(c);
+                if (refresh_tail(c) && !exiting(c)) dry = false;
+            }
+            if (!dry) {
+                const uint32_t want = (uint32_t)__popcll(nm);
+                const int leader = __ffsll((unsigned long long)nm) - 1;
+                // the wave marches a ray of job jcur: that job is not done, so its
+                // slot still holds it, and it is of the wave's group
+                const bool hold = __ballot(active && lslot == c.jcur % kSlots) != 0;
+                uint32_t r0 = 0, b0 = 0, c0 = 0, r1 = 0, b1 = 0, c1 = 0, r2 = 0, b2 = 0, c2 = 0,
+                         r3 = 0, b3 = 0, c3 = 0, nr = 0, jc = c.jcur, unmet = 0;
+                if (c.lane == leader) {
+                    // claim, in job order, from the jobs of the wave's group
+                    uint32_t need = exiting(c) ? 0u : want;
+                    unmet = need == 0;
+                    const uint32_t lim = min(c.seen, c.jcur + kScan);
+                    for (uint32_t jj = c.jcur; need && jj < lim && nr < (uint32_t)kRanges; ++jj) {
+                        const uint32_t sl = jj % kSlots;
+                        const uint32_t nj = c.P->table[sl].n;
+                        const bool held = hold && jj == c.jcur;
+                        bool gone = false;
+                        if (!held) {
+                            const unsigned long long w = __hip_atomic_load(
+                                &c.P->ctl[sl].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            gone = (uint32_t)(w >> 32) != jj || (uint32_t)w >= nj;
+                        }
+                        if (!gone && (held || c.P->table[sl].group == group)) {
+                            // one fetch-and-add (a compare-and-swap loop here stalls
+                            // every wave on one contended word); an add past the end
+                            // only takes what is left, and n < 2^31 keeps the
+                            // overshoot out of the sequence bits.
+                            const unsigned long long o = __hip_atomic_fetch_add(
+                                &c.P->ctl[sl].claim, (unsigned long long)need, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+                            const uint32_t cn = (uint32_t)o;
+                            if ((uint32_t)(o >> 32) != jj) {
+                                // the slot was reused between the check and the add:
+                                // the new job lost rays it can never get back --
+                                // report it
+                                __hip_atomic_store(&c.P->mb->lost, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_SYSTEM);
+                                gone = true;
+                            } else if (cn >= nj) {
+                                gone = true;
+                            } else {
+                                const uint32_t take = min(need, nj - cn);
+                                if (nr == 0) { r0 = sl; b0 = cn; c0 = take; }
+                                else if (nr == 1) { r1 = sl; b1 = cn; c1 = take; }
+                                else if (nr == 2) { r2 = sl; b2 = cn; c2 = take; }
+                                else { r3 = sl; b3 = cn; c3 = take; }
+                                ++nr;
+                                need -= take;
+                                gone = cn + take >= nj;
+                            }
+                        }
+                        if (gone && jj == jc) {  // nothing for anyone below jc
+                            jc = jj + 1;
+                            atomicMax(&c.P->dc->first_open[medium_class(MK)][0], jc);
                         }
                     }
-                    if (gone && jj == jc) {  // nothing for anyone below jc
-                        jc = jj + 1;
-                        atomicMax(&c.dc->first_open[medium_class(MK)][0], jc);
-                    }
+                    unmet |= need;
                 }
-                unmet |= need;
-            }
-            nr = rfl(__shfl(nr, leader));
-            c.jcur = rfl(__shfl(jc, leader));
-            claimed = nr != 0;
-            if (nr < (uint32_t)kRanges && rfl(__shfl(unmet, leader)))
-                dry = true;  // fewer rays than idle lanes: the group has nothing more for now
-            if (nr) {
-                // hand the ranges to the idle lanes in lane order
-                uint32_t k = (uint32_t)__popcll(nm & below);
-                const uint32_t rr[kRanges] = {rfl(__shfl(r0, leader)), rfl(__shfl(r1, leader)),
-                                              rfl(__shfl(r2, leader)), rfl(__shfl(r3, leader))};
-                const uint32_t bb[kRanges] = {rfl(__shfl(b0, leader)), rfl(__shfl(b1, leader)),
-                                              rfl(__shfl(b2, leader)), rfl(__shfl(b3, leader))};
-                const uint32_t cc[kRanges] = {rfl(__shfl(c0, leader)), rfl(__shfl(c1, leader)),
-                                              rfl(__shfl(c2, leader)), rfl(__shfl(c3, leader))};
-                if (!active) {
+                nr = rfl(__shfl(nr, leader));
+                c.jcur = rfl(__shfl(jc, leader));
+                claimed = nr != 0;
+                if (nr < (uint32_t)kRanges && rfl(__shfl(unmet, leader)))
+                    dry = true;  // fewer rays than idle lanes: the group has nothing more for now
+                if (nr) {
+                    // hand the ranges to the idle lanes in lane order
+                    uint32_t k = (uint32_t)__popcll(nm & below);
+                    const uint32_t rr[kRanges] = {rfl(__shfl(r0, leader)), rfl(__shfl(r1, leader)),
+                                                  rfl(__shfl(r2, leader)), rfl(__shfl(r3, leader))};
+                    const uint32_t bb[kRanges] = {rfl(__shfl(b0, leader)), rfl(__shfl(b1, leader)),
+                                                  rfl(__shfl(b2, leader)), rfl(__shfl(b3, leader))};
+                    const uint32_t cc[kRanges] = {rfl(__shfl(c0, leader)), rfl(__shfl(c1, leader)),
+                                                  rfl(__shfl(c2, leader)), rfl(__shfl(c3, leader))};
+                    if (!active) {
 #pragma unroll
-                    for (int q = 0; q < kRanges; ++q) {
-                        if (!fresh && (uint32_t)q < nr) {
-                            if (k < cc[q]) {
-                                L.r = bb[q] + k;
-                                lslot = rr[q];
-                                fresh = true;
-                            } else {
-                                k -= cc[q];
+                        for (int q = 0; q < kRanges; ++q) {
+                            if (!fresh && (uint32_t)q < nr) {
+                                if (k < cc[q]) {
+                                    L.r = bb[q] + k;
+                                    lslot = rr[q];
+                                    fresh = true;
+                                } else {
+                                    k -= cc[q];
+                                }
                             }
                         }
                     }
                 }
             }
-        }
-        // a lane may only start a ray of another job once its count is accounted
-        const bool periodic = ++c.it % kFlushEvery == 0;
-        if (__ballot(fresh && acnt && aslot != lslot) || (periodic && __ballot(acnt)))
-            flush_acc(c, aslot, acnt, asteps);
-        // busy waves also take their turn at activating staged jobs (and at
-        // relaying the host's yield)
-        if (periodic) maybe_activate(c);
-        bool ended = false;
-        if (fresh) {
-            aslot = lslot;
-            grid_invalidate(gc);
-            active = lane_init<MK>(D.m, D.m.rec, D.b, D.t, c.table[lslot].io, L, gc);
-            ended = !active;
+            // a lane may only start a ray of another job once its count is
+            // accounted
+            const bool periodic = c.it % kFlushEvery == 0;
+            if (__ballot(fresh && acnt && aslot != lslot) || (periodic && __ballot(acnt)))
+                flush_acc(c, aslot, acnt, asteps);
+            // busy waves also take their turn at activating staged jobs (and at
+            // relaying the host's yield)
+            if (periodic) maybe_activate(c);
+            if (fresh) {
+                aslot = lslot;
+                grid_invalidate(gc);
+                active = lane_init<MK>(D.m, D.m.rec, D.b, D.t, c.P->table[lslot].io, L, gc);
+                if (!active) {
+                    acnt++;
+                    asteps += L.steps;
+                }
+            }
+            act = __ballot(active);
+            if (!act && (dry || !claimed)) {
+                if (__ballot(acnt)) flush_acc(c, aslot, acnt, asteps);
+                cw.jcur = c.jcur;
+                cw.seen = c.seen;
+                cw.it = c.it;
+                return;
+            }
         }
         if (active) {
-            active = lane_step<MK>(D.m, D.mf, B, D.m.rec, D.b, D.t, c.table[lslot].io, L, gc,
+            active = lane_step<MK>(D.m, D.mf, B, D.m.rec, D.b, D.t, c.P->table[lslot].io, L, gc,
                                    D.dL0, D.eps_tan, D.mrg, D.crit);
-            ended = !active;
-        }
-        if (ended) {
-            acnt++;
-            asteps += L.steps;
+            if (!active) {
+                acnt++;
+                asteps += L.steps;
+            }
         }
         act = __ballot(active);
-        if (!act && (dry || !claimed)) {
-            if (__ballot(acnt)) flush_acc(c, aslot, acnt, asteps);
-            cw.jcur = c.jcur;
-            cw.seen = c.seen;
-            cw.it = c.it;
-            return;
-        }
     }
 }
 
 template <int kClass>
-__global__ __launch_bounds__(256, class_occupancy(kClass)) void serve_kernel(
-    const JobDesc *hdesc, JobDesc *table, JobCtl *ctl, DevCtl *dc, Mailbox *mb, DoneRec *done,
-    JobDesc *wdg) {
+__global__ __launch_bounds__(256, class_occupancy(kClass)) void serve_kernel(SrvPtrs args) {
     __shared__ unsigned long long wacc_all[4][2];
+    const SrvPtrs *__restrict__ P = &args;
+    JobDesc *table = P->table;
+    DevCtl *dc = P->dc;
+    Mailbox *mb = P->mb;
     const int w = threadIdx.x >> 6;
-    JobDesc *mine = wdg + (size_t)blockIdx.x * 4 + w;  // the wave's copy of its group descriptor
+    JobDesc *mine = P->wdg + (size_t)blockIdx.x * 4 + w;  // the wave's copy of its group descriptor
     WaveCtx c;
-    c.hdesc = hdesc;
-    c.table = table;
-    c.ctl = ctl;
-    c.dc = dc;
-    c.mb = mb;
-    c.done = done;
+    c.P = P;
     c.wacc = wacc_all[w];
     c.lane = __lane_id();
     uint32_t *first_open = &dc->first_open[kClass][0];
@@ -1102,7 +1107,8 @@ extern "C" int vrt_server_create(vrt_context_t ctx, size_t hbm_budget, int max_l
         if (max_lanes > 0)
             s->blocks[k] = std::min(s->blocks[k], std::max(1u, (uint32_t)max_lanes / 256u));
         SV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal), "capture");
-        void *args[] = {&s->hdesc, &s->table, &s->ctl, &s->dc, &s->mb, &s->done, &s->wdg};
+        SrvPtrs ptrs{s->hdesc, s->table, s->ctl, s->dc, s->mb, s->done, s->wdg};
+        void *args[] = {&ptrs};
         SV_TRY(hipLaunchKernel(fn, dim3(s->blocks[k]), dim3(256), args, 0, s->stream), "launch");
         SV_TRY(hipStreamEndCapture(s->stream, &s->graph[k]), "capture");
         SV_TRY(hipGraphInstantiate(&s->exec[k], s->graph[k], nullptr, nullptr, 0), "graph");
