@@ -239,7 +239,7 @@ def test_helix(vrt, ctx, orc, precision):
     if precision == "fp64":
         tight(o, g, tol=1e-9)
     else:
-        assert rep["status_mismatch"] == 0 and rep["pos_fail"] == 0 and rep["dir_fail"] == 0
+        assert_parity(rep)
 
 
 MEDIA = {
