@@ -58,8 +58,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("march_fp32c.hip", "lane32.h", "media.h", "vrt_common.h", "dispatch.h")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {  # workload -> (fetch KiB, write KiB, kernel code sha256); profiles/march_fp32c_hbm_traffic.md
-    "freeform": (79073.7, 298252.4, "d2280906beca1abede54b0799afa339666c441258f99a839459071a63f627905"),
-    "grid": (408092384.4, 1585731.9, "d2280906beca1abede54b0799afa339666c441258f99a839459071a63f627905"),
+    "freeform": (79976.9, 294648.2, "65bf19bfe73ed57172fd731d9af57e7ac231ceba7c6809ee805881b7e2def58e"),
+    "grid": (407778959.4, 1583611.5, "65bf19bfe73ed57172fd731d9af57e7ac231ceba7c6809ee805881b7e2def58e"),
 }
 
 
