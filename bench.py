@@ -221,12 +221,13 @@ def cpu_baseline(spec, rays, prm, sample, g_res, aperture):
     if chaotic:
         # rays trapped by repeated TIR (in the sphere, along the lens wall)
         # amplify perturbations up to ~1e4-fold: leave out those whose oracle
-        # result moves by 1e-5 under a float32-sized (1e-7) shift of the launch
-        # point or turn of the launch direction
+        # events change, or whose oracle result moves by more than the bar
+        # (1e-4), under a float32-sized (1e-7) shift of the launch point or
+        # turn of the launch direction (their inputs do not fix them to the bar)
         from parity import exempt, ill_conditioned
 
         bad = ill_conditioned(lambda *a: oracle.trace(*a, n_threads=threads), spec,
-                              (rays[0][:n], rays[1][:n]), prm, delta=1e-7, tol=1e-5, turn=1e-7)
+                              (rays[0][:n], rays[1][:n]), prm, delta=1e-7, tol=1e-4, turn=1e-7)
         r, sub = exempt(r, bad), exempt(sub, bad)
     rep = compare(r, sub, aperture=aperture, spec=spec)
     if chaotic:

@@ -80,15 +80,16 @@ def test_spherical_freeform_medium(vrt, ctx, orc, precision):
         rep = compare(o, g, aperture=2.0, spec=spec)
     else:
         # Rays trapped by repeated TIR in the sphere are chaotic (a quarter of
-        # them amplify a float32-sized launch shift 20-fold): rays whose
-        # oracle result moves by 1e-5 when the launch point moves by 1e-7
-        # (the size of its float32 rounding) or the launch direction turns by
-        # 1e-7 rad are beyond a single-precision march and are left out
-        # (about 8.5 %, at most 10 %).
-        bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-7, tol=1e-5, turn=1e-7)
+        # them amplify a float32-sized launch shift 20-fold).  A ray whose own
+        # oracle result changes its events, or moves by more than the bar
+        # (1e-4), when the launch point moves by 1e-7 (the size of its
+        # float32 rounding) or the launch direction turns by 1e-7 rad is not
+        # determined to the bar by its inputs: those are left out (about
+        # 1.7 %, at most 3 %).
+        bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-7, tol=1e-4, turn=1e-7)
         rep = compare(exempt(o, bad), exempt(g, bad), aperture=2.0, spec=spec)
         rep["ill_conditioned"] = int(bad.sum())
-        assert bad.sum() <= 0.10 * len(bad)
+        assert bad.sum() <= 0.03 * len(bad)
     report(f"spherical {precision}", rep)
     assert_parity(rep)
 
@@ -111,7 +112,7 @@ def test_spherical_centre_takes_a_straight_step(vrt, ctx, orc, precision):
     if precision == "fp64":
         rep = compare(o, g, aperture=2.0, spec=spec)
     else:
-        bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-7, tol=1e-5, turn=1e-7)
+        bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-7, tol=1e-4, turn=1e-7)
         rep = compare(exempt(o, bad), exempt(g, bad), aperture=2.0, spec=spec)
         rep["ill_conditioned"] = int(bad.sum())
     report(f"spherical centre {precision}", rep)
@@ -146,9 +147,10 @@ def test_zernike_lens_medium(vrt, ctx, orc, precision, n_lo, n_hi):
     else:
         # rays that spiral along the wall by repeated boundary TIR amplify a
         # 1e-7 turn of their launch direction up to ~1e4-fold: those whose
-        # oracle result moves by 1e-5 are left out (under 1 %, at most 2 %)
-        bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-7, tol=1e-5, turn=1e-7)
-        assert bad.sum() <= 0.02 * len(bad) and not bad[0]
+        # oracle events change, or whose oracle result moves by more than the
+        # bar (1e-4), are left out (about 0.3 %, at most 1 %)
+        bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-7, tol=1e-4, turn=1e-7)
+        assert bad.sum() <= 0.01 * len(bad) and not bad[0]
         rep = compare(exempt(o, bad), exempt(g, bad), aperture=4.2, spec=spec)
         rep["ill_conditioned"] = int(bad.sum())
     report(f"zernike {precision} n=({n_lo}, {n_hi})", rep)

@@ -114,8 +114,11 @@ def test_random_medium_parity(vrt, ctx, orc, seed):
             if precision == "fp64":
                 rep = compare(o, g, aperture=2.0 * size, spec=spec)
             else:
-                bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-7, tol=1e-5, turn=1e-7)
-                assert bad.sum() <= 0.10 * len(bad)
+                # rays whose own oracle events change, or whose oracle result
+                # moves by more than the bar, under a float32-sized launch
+                # perturbation are not fixed to the bar by their inputs
+                bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-7, tol=1e-4, turn=1e-7)
+                assert bad.sum() <= 0.03 * len(bad)
                 rep = compare(exempt(o, bad), exempt(g, bad), aperture=2.0 * size, spec=spec)
                 rep["ill_conditioned"] = int(bad.sum())
             print(f"\n[random {seed} {spec['kind']} in {spec['boundary']['kind']} {precision}] "

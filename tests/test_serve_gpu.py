@@ -155,11 +155,12 @@ def test_served_results_meet_the_parity_bar(vrt, ctx, media):
         o = oracle.trace(specs[mi], rays, prm)
         if specs[mi]["kind"] in ("spherical", "zernike"):
             # repeated TIR in the sphere or along the lens wall: leave out the
-            # rays whose oracle result moves by 1e-5 under a float32-sized
-            # (1e-7) shift of the launch point or turn of the launch direction
-            bad = ill_conditioned(oracle.trace, specs[mi], rays, prm, delta=1e-7, tol=1e-5,
+            # rays whose oracle events change, or whose oracle result moves by
+            # more than the bar (1e-4), under a float32-sized (1e-7) shift of
+            # the launch point or turn of the launch direction
+            bad = ill_conditioned(oracle.trace, specs[mi], rays, prm, delta=1e-7, tol=1e-4,
                                   turn=1e-7)
-            assert bad.sum() <= 0.10 * len(bad)
+            assert bad.sum() <= 0.03 * len(bad)
             o, r = exempt(o, bad), exempt(r, bad)
         ap = 2.0 if specs[mi]["boundary"]["kind"] == "sphere" else (
             10.0 if specs[mi]["kind"] == "fiber" else 4.2 if specs[mi]["kind"] == "zernike" else 1.0)
