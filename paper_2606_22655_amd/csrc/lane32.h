@@ -439,12 +439,12 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
         float ni, gx, gy, gz, dn, nb = 0.f, nl = 0.f;
         double nd = 0.0;
         const float n_last = L.nlb;  // float-evaluated analytic media keep nld = 0
+        double n64 = 0.0;  // media taken in double: n and grad n at P_i
+        d3 g64 = mk(0.0, 0.0, 0.0);
         if constexpr (kIndexIn64<MK>) {
             // n and grad n in double at the compensated position; n(P_{i-1}) is
             // kept as nlb + nld, so dn is a difference of two double indices
             const d3 P64 = mk((double)L.Phx - L.Pcx, (double)L.Phy - L.Pcy, (double)L.Phz - L.Pcz);
-            double n64;
-            d3 g64;
             med64<MK>(m, P64, n64, g64);
             ni = nb = (float)n64;
             nd = n64 - (double)nb;
@@ -503,21 +503,36 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
             } else {
                 const float m1 = -dn * frcp(ni);  // mu_i - 1, mu_i = n_{i-1} / n_i
                 if (c * c <= 4.0f * fabsf(m1) * (2.0f + m1)) {
-                    // near grazing: the step is taken in double -- n at P_i and
-                    // P_{i-1}, the normal, c, D and R (Eqs. (5), (9)-(10), (19)-(20))
-                    const d3 P64 = mk((double)L.Phx - L.Pcx, (double)L.Phy - L.Pcy,
-                                      (double)L.Phz - L.Pcz);
-                    const d3 Pp64 = P64 - mk((double)L.sx, (double)L.sy, (double)L.sz);
+                    // near grazing: the step is taken in double -- n and the
+                    // normal at P_i, c, D and R (Eqs. (5), (9)-(10), (19)-(20)).
+                    // Media taken in double have n and grad n at P_i in double
+                    // already and evaluate n(P_{i-1}) again at P_i - s; media
+                    // evaluated in float take mu = 1 + (mu - 1) from the step's
+                    // index difference (its error, ~1e-11, moves the critical
+                    // angle by ~1e-9 rad).
                     const d3 I64 = mk((double)L.Ihx - L.Icx, (double)L.Ihy - L.Icy,
                                       (double)L.Ihz - L.Icz);
-                    d3 g64, gp;
-                    double ni64, np64;
-                    med64<MK>(m, P64, ni64, g64);
-                    med64<MK>(m, Pp64, np64, gp);
-                    const double gl = sqrt(dot(g64, g64));
-                    const d3 N = mk(g64.x / gl, g64.y / gl, g64.z / gl);
+                    double ni64, mu, np64;
+                    d3 gi64;
+                    if constexpr (kIndexIn64<MK>) {
+                        const d3 Pp64 = mk((double)L.Phx - L.Pcx - (double)L.sx,
+                                           (double)L.Phy - L.Pcy - (double)L.sy,
+                                           (double)L.Phz - L.Pcz - (double)L.sz);
+                        d3 gp;
+                        med64<MK>(m, Pp64, np64, gp);
+                        ni64 = n64;
+                        gi64 = g64;
+                        mu = np64 / ni64;
+                    } else {
+                        const d3 P64 = mk((double)L.Phx - L.Pcx, (double)L.Phy - L.Pcy,
+                                          (double)L.Phz - L.Pcz);
+                        med64<MK>(m, P64, ni64, gi64);
+                        mu = 1.0 + (double)m1;
+                        np64 = mu * ni64;
+                    }
+                    const double gl = sqrt(dot(gi64, gi64));
+                    const d3 N = mk(gi64.x / gl, gi64.y / gl, gi64.z / gl);
                     const double cd = dot(N, I64);
-                    const double mu = np64 / ni64;
                     const double D = 1.0 - mu * mu * (1.0 - cd * cd);
                     if (near_critical(mu, cd, D, t.crit_rad)) L.flags |= VRT_FLAG_NEAR_CRITICAL;
                     if (mu < 1.0 && fabs(cd) < t.crit_rad) L.flags |= VRT_FLAG_NEAR_GRAZING;
