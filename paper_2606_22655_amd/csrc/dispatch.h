@@ -5,6 +5,8 @@
 
 namespace vrt {
 
+struct EntryState;  // lane32.h
+
 struct LaunchArgs {
     MediumDev m;
     MedF mf;
@@ -18,7 +20,12 @@ struct LaunchArgs {
     int num_cu;
     int blocks_per_cu;  // FP32_COMP persistent grid: blocks of 256 lanes per CU (0 = default)
     uint32_t max_blocks;  // FP32_COMP persistent grid: cap on the blocks (0 = none)
+    EntryState *entry;    // FP32_COMP: n entry states for media marched from them, or null
 };
+
+// FP32_COMP: whether a launch on a medium of this kind runs the entry kernel
+// first when given room for the entry states
+bool fp32c_pre_entry(int kind);
 
 hipError_t launch_march_fp64(const LaunchArgs &a);
 hipError_t launch_march_fp32c(const LaunchArgs &a);

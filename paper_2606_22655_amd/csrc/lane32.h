@@ -279,6 +279,7 @@ __device__ bool lane_init(const MediumDev &m, const float4 *__restrict__ rec, co
         split(I.y, L.Ihy, L.Icy);
         split(I.z, L.Ihz, L.Icz);
         index_at_event<MK>(m, gc, P0, L);
+        L.Delta = L.Dl = 0.0f;  // set by the first decision (the grid's request reads it)
         L.pending = false;
         return true;
     }
@@ -309,6 +310,66 @@ __device__ bool lane_init(const MediumDev &m, const float4 *__restrict__ rec, co
     index_at_event<MK>(m, gc, P, L);
     step_len64(t.dL0 / n_in, L.Delta, L.Dl);
     L.pending = true;
+    return true;
+}
+
+// The state of a ray after its launch and entry (lane_init), as the entry
+// kernel leaves it for a march kernel that starts rays from it (lane_load):
+// the march kernel then holds no double-precision entry code, which for the
+// grid medium is where its registers peak.  80 bytes.
+struct alignas(16) EntryState {
+    float Phx, Phy, Phz, Pcx, Pcy, Pcz;
+    float Ihx, Ihy, Ihz, Icx, Icy, Icz;
+    float nlb, nlo;
+    double nld;
+    float Delta, Dl;
+    uint32_t flags;
+    uint32_t state;  // kEntered, kInside, or kEnded (outputs already written)
+};
+static_assert(sizeof(EntryState) == 80, "entry state layout");
+constexpr uint32_t kEntered = 0, kInside = 1, kEnded = 2;
+
+template <int MK>
+__device__ __forceinline__ void entry_store(const Lane &L, bool active, EntryState &e) {
+    if (!active) {
+        e = EntryState{};
+        e.state = kEnded;
+        return;
+    }
+    e.Phx = L.Phx; e.Phy = L.Phy; e.Phz = L.Phz;
+    e.Pcx = L.Pcx; e.Pcy = L.Pcy; e.Pcz = L.Pcz;
+    e.Ihx = L.Ihx; e.Ihy = L.Ihy; e.Ihz = L.Ihz;
+    e.Icx = L.Icx; e.Icy = L.Icy; e.Icz = L.Icz;
+    e.nlb = L.nlb;
+    e.nlo = MK == VRT_MEDIUM_GRID ? L.nlo : 0.0f;
+    e.nld = MK == VRT_MEDIUM_GRID ? 0.0 : L.nld;
+    e.Delta = L.Delta;
+    e.Dl = L.Dl;
+    e.flags = L.flags;
+    e.state = L.pending ? kEntered : kInside;
+}
+
+// Start ray L.r from its stored entry state.  Returns false if the ray ended
+// at its launch or entry (its outputs are written already).
+template <int MK>
+__device__ __forceinline__ bool lane_load(const EntryState *__restrict__ es, Lane &L,
+                                          GridCache &gc) {
+    const EntryState &e = es[L.r];
+    if (e.state == kEnded) return false;
+    L.steps = L.ntir = L.nbtir = 0;
+    L.flags = e.flags;
+    L.sx = L.sy = L.sz = 0.0f;
+    L.Phx = e.Phx; L.Phy = e.Phy; L.Phz = e.Phz;
+    L.Pcx = e.Pcx; L.Pcy = e.Pcy; L.Pcz = e.Pcz;
+    L.Ihx = e.Ihx; L.Ihy = e.Ihy; L.Ihz = e.Ihz;
+    L.Icx = e.Icx; L.Icy = e.Icy; L.Icz = e.Icz;
+    L.nlb = e.nlb;
+    if constexpr (MK == VRT_MEDIUM_GRID) L.nlo = e.nlo;
+    else L.nld = e.nld;
+    L.Delta = e.Delta;
+    L.Dl = e.Dl;
+    L.pending = e.state == kEntered;
+    grid_invalidate(gc);
     return true;
 }
 

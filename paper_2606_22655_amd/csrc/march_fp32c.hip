@@ -15,10 +15,40 @@ struct Launch32 {
     RaysDev<float> io;
 };
 
+// Media whose launches run the entry kernel first when the library can hold
+// the entry states (80 bytes per ray): without the double-precision entry
+// code the grid march fits 3 waves per SIMD instead of 2.
 template <int MK>
-__global__ __launch_bounds__(256, MK == VRT_MEDIUM_GRID || MK == VRT_MEDIUM_ZERNIKE ? 2 : 3) void march_fp32c_kernel(
+constexpr bool kPreEntry = MK == VRT_MEDIUM_GRID;
+
+template <int MK, bool kPre>
+constexpr int march_occupancy() {
+    return (MK == VRT_MEDIUM_GRID && !kPre) || MK == VRT_MEDIUM_ZERNIKE ? 2 : 3;
+}
+
+// One thread per ray: launch, flight to the enclosing surface and entry
+// refraction (lane_init); rays that end there are written, the others'
+// states stored for the march.
+template <int MK>
+__global__ __launch_bounds__(256) void entry_kernel(Launch32 desc, const float4 *__restrict__ rec,
+                                                    uint32_t n, EntryState *__restrict__ es) {
+    const uint32_t r = blockIdx.x * 256u + threadIdx.x;
+    if (r >= n) return;
+    const Launch32 *__restrict__ D = &desc;
+    Lane L;
+    GridCache gc;
+    grid_invalidate(gc);
+    L.r = r;
+    const bool active = lane_init<MK>(D->m, rec, D->b, D->t, D->io, L, gc);
+    EntryState e;
+    entry_store<MK>(L, active, e);
+    es[r] = e;
+}
+
+template <int MK, bool kPre>
+__global__ __launch_bounds__(256, (march_occupancy<MK, kPre>())) void march_fp32c_kernel(
     Launch32 desc, const float *__restrict__ bumps, const float4 *__restrict__ rec, uint32_t n,
-    uint32_t *queue) {
+    uint32_t *queue, const EntryState *__restrict__ es) {
     const Launch32 *__restrict__ D = &desc;
     const MediumDev &m = D->m;
     const MedF &mf = D->mf;
@@ -53,7 +83,11 @@ __global__ __launch_bounds__(256, MK == VRT_MEDIUM_GRID || MK == VRT_MEDIUM_ZERN
                     done = true;
                 } else {
                     L.r = r;
-                    active = lane_init<MK>(m, rec, b, t, io, L, gc);
+                    if constexpr (kPre) {
+                        active = lane_load<MK>(es, L, gc);
+                    } else {
+                        active = lane_init<MK>(m, rec, b, t, io, L, gc);
+                    }
                 }
             }
             done_m = __ballot(done);
@@ -68,13 +102,13 @@ __global__ __launch_bounds__(256, MK == VRT_MEDIUM_GRID || MK == VRT_MEDIUM_ZERN
 
 __global__ void queue_reset_kernel(uint32_t *q) { *q = 0u; }
 
-template <int MK>
+template <int MK, bool kPre>
 static hipError_t launch32(const LaunchArgs &a) {
     static int occ = -1;
     if (occ < 0) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march_fp32c_kernel<MK>, 256, 0) !=
-                hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march_fp32c_kernel<MK, kPre>, 256,
+                                                         0) != hipSuccess ||
             nb <= 0)
             nb = 4;
         occ = nb;
@@ -86,9 +120,27 @@ static hipError_t launch32(const LaunchArgs &a) {
     if (a.max_blocks > 0 && blocks > a.max_blocks) blocks = a.max_blocks;
     hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, a.stream, a.queue);
     const Launch32 desc{a.m, a.mf, a.b, a.t, a.io32};
-    hipLaunchKernelGGL(march_fp32c_kernel<MK>, dim3(blocks), dim3(256), 0, a.stream, desc,
-                       a.m.bumps_f, a.m.rec, a.n, a.queue);
+    if constexpr (kPre)
+        hipLaunchKernelGGL(entry_kernel<MK>, dim3((a.n + 255u) / 256u), dim3(256), 0, a.stream,
+                           desc, a.m.rec, a.n, a.entry);
+    hipLaunchKernelGGL((march_fp32c_kernel<MK, kPre>), dim3(blocks), dim3(256), 0, a.stream, desc,
+                       a.m.bumps_f, a.m.rec, a.n, a.queue, (const EntryState *)a.entry);
     return hipGetLastError();
+}
+
+template <int MK>
+static hipError_t launch32(const LaunchArgs &a) {
+    if constexpr (kPreEntry<MK>) {
+        if (a.entry) return launch32<MK, true>(a);
+    }
+    return launch32<MK, false>(a);
+}
+
+bool fp32c_pre_entry(int kind) {
+    switch (kind) {
+    case VRT_MEDIUM_GRID: return kPreEntry<VRT_MEDIUM_GRID>;
+    default: return false;
+    }
 }
 
 hipError_t launch_march_fp32c(const LaunchArgs &a) {

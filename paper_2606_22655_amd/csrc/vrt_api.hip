@@ -701,7 +701,22 @@ int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, s
                         "vrt_trace: hipStreamWaitEvent");
         }
         a.queue = ctx->queues + (size_t)slot * kQueueStride;
+        // media marched from stored entry states get room for them from the
+        // stream-ordered pool, freed behind the march on the same stream; a
+        // captured launch, or one the pool cannot serve, enters rays inline
+        a.entry = nullptr;
+        if (!captured && ctx->async_pools && fp32c_pre_entry(m->dev.kind)) {
+            void *buf = nullptr;
+            if (hipMallocAsync(&buf, (size_t)n_rays * 80u, (hipStream_t)stream) == hipSuccess)
+                a.entry = (EntryState *)buf;
+            else
+                (void)hipGetLastError();  // not sticky: the launch goes on without the states
+        }
         e = launch_march_fp32c(a);
+        if (a.entry) {
+            const hipError_t ef = hipFreeAsync(a.entry, (hipStream_t)stream);
+            if (e == hipSuccess) e = ef;
+        }
         if (e == hipSuccess && !captured) {
             e = hipEventRecord(ctx->slot_ev[slot], (hipStream_t)stream);
             if (e == hipSuccess) ctx->slot_recorded[slot] = true;
