@@ -17,13 +17,13 @@ struct Launch32 {
 
 // Media whose launches run the entry kernel first when the library can hold
 // the entry states (80 bytes per ray): without the double-precision entry
-// code the grid march fits 3 waves per SIMD instead of 2.
+// code the grid and Zernike-lens marches fit 3 waves per SIMD instead of 2.
 template <int MK>
-constexpr bool kPreEntry = MK == VRT_MEDIUM_GRID;
+constexpr bool kPreEntry = MK == VRT_MEDIUM_GRID || MK == VRT_MEDIUM_ZERNIKE;
 
 template <int MK, bool kPre>
 constexpr int march_occupancy() {
-    return (MK == VRT_MEDIUM_GRID && !kPre) || MK == VRT_MEDIUM_ZERNIKE ? 2 : 3;
+    return (MK == VRT_MEDIUM_GRID || MK == VRT_MEDIUM_ZERNIKE) && !kPre ? 2 : 3;
 }
 
 // One thread per ray: launch, flight to the enclosing surface and entry
@@ -139,6 +139,7 @@ static hipError_t launch32(const LaunchArgs &a) {
 bool fp32c_pre_entry(int kind) {
     switch (kind) {
     case VRT_MEDIUM_GRID: return kPreEntry<VRT_MEDIUM_GRID>;
+    case VRT_MEDIUM_ZERNIKE: return kPreEntry<VRT_MEDIUM_ZERNIKE>;
     default: return false;
     }
 }
