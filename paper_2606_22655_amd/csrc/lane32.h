@@ -384,8 +384,7 @@ __device__ __forceinline__ bool lane_load(const EntryState *__restrict__ es, Lan
 // Eqs. (9)-(10) as for the other media; TIR reflects by -2 c N (Eq. (20)) and
 // moves on with Delta_{i-1} = dL0 / n_{i-1}.  The tangential rule probes n in
 // double from the node values.  Sets the direction increment, L.Delta, L.Dl
-// and the index of P_i as the next step's n(P_{i-1}), and requests the records
-// of the cell the move is predicted to enter.
+// and the index of P_i as the next step's n(P_{i-1}).
 __device__ __forceinline__ void grid_decide(const MediumDev &m, const float4 *__restrict__ rec,
                                             const TraceDev &t, Lane &L, GridCache &gc, float dL0,
                                             float eps_tan, float crit_f, float &incx, float &incy,
@@ -400,30 +399,6 @@ __device__ __forceinline__ void grid_decide(const MediumDev &m, const float4 *__
     const float nb = gc.v[0].x;
     const float ni = nb + delta, nl = (nb - ni) + delta;  // n(P_i) = ni + nl
     const float dn = (nb - L.nlb) + (delta - L.nlo);      // nb - nlb exact: nearby node values
-    // n(P_{i-1}) as a float pair, for the step after a TIR (Eq. (20)), and
-    // the index of P_i as the next step's n(P_{i-1}): both taken before the
-    // cached records are replaced below ("+ 0" is exact, nb > 0; it keeps the
-    // value apart from the record it was read from)
-    const float nph = L.nlb + L.nlo, npl = (L.nlb - nph) + L.nlo;
-    L.nlb = nb + 0.0f;
-    L.nlo = delta;
-    {
-        // The blend above was the last use of the cached records: request those
-        // of the cell the ray is about to enter now, so that they arrive while
-        // the decision and the move are computed.  The cell is predicted from
-        // the last step's length along the current direction; the next step's
-        // cell test checks it against the true position (a wrong guess costs a
-        // second fetch there, as without the prediction).
-        const float s = L.Delta;
-        const float qx = fx + s * L.Ihx * m.finv_h[0], qy = fy + s * L.Ihy * m.finv_h[1],
-                    qz = fz + s * L.Ihz * m.finv_h[2];
-        if (!(qx >= 0.0f && qx < 1.0f && qy >= 0.0f && qy < 1.0f && qz >= 0.0f && qz < 1.0f)) {
-            const int ci = min(max(gc.ci + (int)floorf(qx), 0), m.nx - 2);
-            const int cj = min(max(gc.cj + (int)floorf(qy), 0), m.ny - 2);
-            const int ck = min(max(gc.ck + (int)floorf(qz), 0), m.nz - 2);
-            if (ci != gc.ci || cj != gc.cj || ck != gc.ck) grid_fetch(m, rec, gc, ci, cj, ck);
-        }
-    }
     incx = incy = incz = 0.0f;
     const float gl2 = gx * gx + gy * gy + gz * gz;
     if (!(gl2 > 0.0f) || !isfinite(gl2)) {  // cases (ii)/(iii): straight
@@ -464,6 +439,7 @@ __device__ __forceinline__ void grid_decide(const MediumDev &m, const float4 *__
                 incx = c2 * Nx;
                 incy = c2 * Ny;
                 incz = c2 * Nz;
+                const float nph = L.nlb + L.nlo, npl = (L.nlb - nph) + L.nlo;
                 step_len(dL0, dL0l, nph, npl, L.Delta, L.Dl);
                 L.ntir++;
             } else {  // Eqs. (9)-(10) as an increment
@@ -477,6 +453,8 @@ __device__ __forceinline__ void grid_decide(const MediumDev &m, const float4 *__
             }
         }
     }
+    L.nlb = nb;
+    L.nlo = delta;
 }
 
 // One decision (unless pending) and one move.  Returns false when the ray
