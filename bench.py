@@ -58,8 +58,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("march_fp32c.hip", "lane32.h", "media.h", "vrt_common.h", "dispatch.h")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {  # workload -> (fetch KiB, write KiB, kernel code sha256); profiles/march_fp32c_hbm_traffic.md
-    "freeform": (79817.7, 295311.7, "de423e8f847c887f6c315ad16d673de4f8208457319a8a5f75724498cf1cfc32"),
-    "grid": (407780673.5, 1583618.6, "de423e8f847c887f6c315ad16d673de4f8208457319a8a5f75724498cf1cfc32"),
+    "freeform": (80267.1, 297006.9, "b786c5200aa8cce6b5cf8939c6cb2df0cc9edb42560c6aabb92aea15e2220013"),
+    "grid": (427678788.5, 1578010.4, "b786c5200aa8cce6b5cf8939c6cb2df0cc9edb42560c6aabb92aea15e2220013"),
 }
 
 
