@@ -224,7 +224,14 @@ int vrt_medium_device_bytes(vrt_medium_t m, size_t *out);
  * counters, each guarded by an event (a launch waits on its stream for the
  * counter's previous launch); a launch captured in a graph keeps a counter of
  * its own for the context's life (960 of them), so replays never share one
- * with any other launch. */
+ * with any other launch.
+ * Device memory: an eager VRT_FP32_COMP launch on a grid or Zernike-lens
+ * medium first enters every ray (launch, flight to the enclosing surface,
+ * entry refraction) in a kernel of its own and keeps the 80-byte states in
+ * memory taken from the device's stream-ordered pool on `stream` and returned
+ * to it behind the march on the same stream.  A launch captured in a graph,
+ * or one the pool cannot serve, enters the rays inside the march instead;
+ * the results are the same bit for bit. */
 int vrt_trace(vrt_medium_t m, const vrt_trace_params *p, const vrt_rays *rays, size_t n_rays,
               void *stream);
 
