@@ -92,6 +92,42 @@ def test_trace_captured_in_a_graph_replays_the_eager_result(vrt, ctx):
         med.close()
 
 
+def test_grid_trace_captured_in_a_graph_equals_the_eager_one(vrt, ctx):
+    """An eager single-precision trace on a grid medium enters its rays in a
+    kernel of its own (states in stream-ordered memory); the same trace
+    captured in a graph enters them inside the march.  Both give the same
+    results bit for bit, on every replay."""
+    import torch
+
+    spec = workloads.grid_medium(workloads.noise_grid(48, 531))
+    rays = workloads.face_cone_rays(6000, 532, 30.0)
+    prm = workloads.trace_params(5e-4, 60000)
+    med = vrt.Medium(ctx, spec)
+    try:
+        b = vrt.RayBatch(rays[0], rays[1], "fp32c")
+        vrt.trace(med, b, prm, "fp32c")
+        torch.cuda.synchronize()
+        eager = b.results()
+        assert (eager["status"] == 0).mean() > 0.9
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                vrt.trace(med, b, prm, "fp32c", stream=torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        for k in range(3):
+            b.out.fill_(float("nan"))
+            b.u32.fill_(-1)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert same(eager, b.results()), k
+        del g
+    finally:
+        med.close()
+
+
 def test_graph_replays_beside_more_than_1024_eager_traces(vrt, ctx):
     """A single-precision trace captured in a graph keeps a ray-queue counter
     of its own: replayed while 1,100 eager traces (more than the context's
