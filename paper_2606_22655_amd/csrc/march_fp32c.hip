@@ -1,5 +1,7 @@
 // march_fp32c.hip -- persistent batch kernel of the single-precision
-// compensated VRT march: lanes refilled from the batch's ray queue.
+// compensated VRT march: lanes refilled from the batch's ray queue.  For the
+// grid and Zernike-lens media an eager launch first enters every ray in a
+// kernel of its own and the march starts rays from the stored states.
 #include "lane32.h"
 
 namespace vrt {
