@@ -175,6 +175,54 @@ def test_grid_fp32c_statistics(vrt, ctx, grid_case):
     assert_stats(rep)
 
 
+# ---------------------------------------------------------------------------
+# grids sampled from smooth fields: whole paths per ray
+#
+# Unlike the quantized grid, these are not chaotic for the march, so the FP32
+# path is held to the bar on whole paths: cell crossings, the boundary TIR and
+# surface events of the box, and exits.  "graded" falls off away from the
+# box's axis (interior TIR bends rays back towards it, as in a graded-index
+# fiber: ~4,000 TIRs at incidences within 1e-3 rad of grazing); "ripple" is a
+# weak periodic modulation over a slope.  Set aside, as for the spherical
+# medium: rays whose own oracle result moves (events, or the exit by more than
+# 1e-4) when the launch point is shifted or the launch direction turned by
+# 3e-7 -- the size of the FP32 march's own accumulated error here (its
+# blended gradient carries a few float ulp of the corners' gradients, which
+# turns the normal by up to ~5e-7 rad per step).  Found this way: rays whose
+# path holds a TIR decision within a few 1e-6 rad of the critical angle at an
+# incidence within 1e-3 rad of grazing, where that error is a percent of the
+# margin.
+# ---------------------------------------------------------------------------
+def smooth_grid(name, N=48):
+    x = np.linspace(0.0, 1.0, N)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")  # node arrays indexed [z, y, x]
+    if name == "graded":
+        n = 1.6 - 0.2 * ((X - 0.5) ** 2 + (Y - 0.5) ** 2) + 0.05 * Z
+    else:
+        n = 1.5 + 0.02 * np.sin(2.0 * np.pi * X) * np.cos(2.0 * np.pi * Y) + 0.05 * Z
+    return workloads.grid_medium(n.astype(np.float32))
+
+
+@pytest.mark.parametrize("name", ["graded", "ripple"])
+def test_grid_smooth_full_paths(vrt, ctx, orc, name):
+    spec = smooth_grid(name)
+    rays = workloads.face_cone_rays(4096, 311, 30.0)
+    prm = workloads.trace_params(1e-3, 20000)
+    o = orc.trace(spec, rays, prm)
+    assert (o["nbtir"] > 0).sum() > 500  # the boundary path is exercised
+    if name == "graded":
+        assert o["ntir"].sum() > 1000  # and the interior TIR
+    g64 = run_gpu(vrt, ctx, spec, rays, prm, "fp64")
+    tight(o, g64, tol=1e-12)
+    g = run_gpu(vrt, ctx, spec, rays, prm, "fp32c")
+    bad = ill_conditioned(orc.trace, spec, rays, prm, delta=3e-7, tol=1e-4, turn=3e-7)
+    rep = compare(exempt(o, bad), exempt(g, bad), aperture=1.0, spec=spec)
+    rep["ill_conditioned"] = int(bad.sum())
+    report(f"{name} grid fp32c full paths", rep)
+    assert bad.sum() <= 0.01 * len(bad)
+    assert_parity(rep)
+
+
 def test_grid_full_size_sampled(vrt, ctx, orc):
     """The 4M-ray quantized-grid configuration in the launch configuration
     the benchmark times.  Properties of every exit state; a seeded sample of
