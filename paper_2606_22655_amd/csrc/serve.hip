@@ -66,6 +66,7 @@
 
 #include "api_internal.h"
 #include "lane32.h"
+#include "pool.h"
 
 namespace vrt {
 namespace serve {
@@ -560,54 +561,6 @@ struct HostJob {
     uint64_t steps = 0;
     double t_submit = 0, t_admit = 0, t_start = 0, t_retired = 0, t_done = 0;
     hsa_signal_t sig{0};  // completion of the job's input or output copies
-};
-
-// First-fit allocator over [0, size) in 256-byte units.
-class Pool {
-  public:
-    void reset(size_t size) {
-        free_.clear();
-        free_[0] = size;
-        used_ = peak_ = 0;
-    }
-    bool alloc(size_t bytes, size_t *off) {
-        bytes = (bytes + 255) & ~(size_t)255;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes, at = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                used_ += bytes;
-                peak_ = used_ > peak_ ? used_ : peak_;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = (bytes + 255) & ~(size_t)255;
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
-
-  private:
-    std::map<size_t, size_t> free_;
-    size_t used_ = 0, peak_ = 0;
 };
 
 constexpr size_t kRayBytes = 6 * 4 + 6 * 4 + 5 * 4;  // inputs, outputs, per-ray words
