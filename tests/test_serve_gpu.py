@@ -191,6 +191,31 @@ def test_served_equals_batch_trace_for_every_medium_kind(vrt, ctx, media):
         assert not diff, (specs[mi]["kind"], diff)
 
 
+def test_served_random_grids_equal_batch(vrt, ctx):
+    """Grid jobs on four seeded random grids (anisotropic node counts, boxes
+    off the origin with unequal sides, smooth or quantized values, ambient
+    index 1 or 1.33) served together: every ray equals the batch trace of the
+    same rays, bitwise, over whole paths."""
+    from test_random_media_gpu import grid_case, outside_rays
+
+    cases = [grid_case(seed) for seed in range(4)]
+    meds = [vrt.Medium(ctx, spec) for spec, _, _ in cases]
+    try:
+        prm = {"dL0": 2e-3, "max_steps": 20000, "crit_rad": 1e-6, "tie_eps": 1e-7}
+        jobs = [(mi, outside_rays(1500, 200 + mi, size), prm)
+                for mi, (_, size, _) in enumerate(cases)]
+        res, _, _ = serve_all(vrt, ctx, meds, jobs)
+        for (mi, rays, _), r in zip(jobs, res):
+            ref = batch_trace(vrt, ctx, meds[mi], rays, prm)
+            assert int(ref["nbtir"].sum()) > 0  # boundary TIR is on these paths
+            diff = [k for k in ("P", "D", "status", "steps", "ntir", "nbtir", "flags")
+                    if not np.array_equal(ref[k], r[k])]
+            assert not diff, (cases[mi][2], diff)
+    finally:
+        for m in meds:
+            m.close()
+
+
 def test_served_grid_jobs_first_128_moves(vrt, ctx, orc):
     """Grid jobs served on a 48^3 and a 256^3 quantized grid, truncated after
     128 moves, against the oracle per ray under the pass rule (the grid is
