@@ -90,7 +90,8 @@ def traffic_bytes(workload):
 
 def algo_flops_per_step(workload, K=16):
     """Algorithmic FP32 work of one ray-step (FMA = 2, add/mul/cmp = 1,
-    exp/sqrt/rsqrt/div = 1), derived in DESIGN.md."""
+    exp/sqrt/rsqrt/div = 1): the operations the method itself needs per step,
+    counted term by term below."""
     march = 50  # normal, N.I, mu, D, gamma, R = mu I + gamma N, Delta, move, surface test
     if workload == "freeform":
         return 19 * K + march  # per bump: P-c 3, r^2 5, scale 1, exp 1, A e 1, n+= 1, grad 7
