@@ -85,6 +85,13 @@ def media_cases():
         workloads.trace_params(1e-3, 20000), 1000
     grid = workloads.grid_medium(workloads.noise_grid(24, 505))
     yield "grid", grid, workloads.face_cone_rays(70, 36, 25.0), workloads.trace_params(2e-3, 300), 200
+    yield "spherical", workloads.spherical_medium(), workloads.sphere_aimed_rays(40, 37), \
+        workloads.trace_params(2e-3, 20000), 3000
+    # a grid of 34 x 2 x 32 nodes in a box off the origin, ambient index 1.33
+    from test_random_media_gpu import grid_case, outside_rays
+
+    spec, size, _ = grid_case(3)
+    yield "flat grid", spec, outside_rays(40, 38, size), workloads.trace_params(2e-3, 20000), 3000
 
 
 @pytest.mark.parametrize("case", [c[0] for c in media_cases()])
