@@ -363,7 +363,9 @@ int vrt_grid_loss_grad(vrt_medium_t grid, const vrt_trace_params *p, const vrt_a
  * 2 ms after the last job retired; relaunches replay a captured hipGraph.
  * While it runs it occupies every compute unit it was sized for, so other
  * kernels on the device wait for it.  Host scheduling runs on a thread owned
- * by the server.
+ * by the server; submit, query, wait and stats may be called from several
+ * host threads at once (they serialise on the server's lock), destroy from
+ * one thread once the others are done with the server.
  *
  * Not from the paper: the paper traces rays one at a time; this is the batch
  * scheduling of its per-ray march (Sec. II).

@@ -191,6 +191,46 @@ def test_served_equals_batch_trace_for_every_medium_kind(vrt, ctx, media):
         assert not diff, (specs[mi]["kind"], diff)
 
 
+def test_submissions_from_several_threads(vrt, ctx, media):
+    """Four host threads share one server, each submitting six jobs of mixed
+    sizes on mixed media and waiting for them; every served ray equals the
+    batch trace of the same rays, bitwise, and the server's totals add up."""
+    import threading
+
+    specs, meds = media
+    srv = vrt.Server(ctx, 1 << 30)
+    results, errors = {}, []
+
+    def worker(w):
+        try:
+            jobs = mixed_jobs(specs, 40 + w, [3000, 17, 900, 4000, 256, 1500])
+            bufs = [vrt.HostRays(P0, d0) for (_, (P0, d0), _) in jobs]
+            ids = [srv.submit(meds[mi], b, prm) for (mi, _, prm), b in zip(jobs, bufs)]
+            infos = [srv.wait(j, 120.0) for j in ids]
+            results[w] = (jobs, [b.results() for b in bufs], infos)
+        except Exception as e:  # reported by the main thread
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=worker, args=(w,)) for w in range(4)]
+    try:
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(300.0)
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert not errors, errors
+    assert sorted(results) == [0, 1, 2, 3]
+    n_jobs = sum(len(v[0]) for v in results.values())
+    n_rays = sum(sum(len(rays[0]) for (_, rays, _) in v[0]) for v in results.values())
+    assert stats["jobs_done"] == n_jobs and stats["rays_done"] == n_rays
+    for jobs, res, infos in results.values():
+        for (mi, rays, prm), r, i in zip(jobs, res, infos):
+            assert i["state"] == "DONE" and i["error"] == 0
+            assert same(batch_trace(vrt, ctx, meds[mi], rays, prm), r), specs[mi]["kind"]
+
+
 def test_served_random_grids_equal_batch(vrt, ctx):
     """Grid jobs on four seeded random grids (anisotropic node counts, boxes
     off the origin with unequal sides, smooth or quantized values, ambient
