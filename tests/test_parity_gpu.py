@@ -394,12 +394,24 @@ def test_counters_match_outputs(vrt, ctx):
     assert c["flagged_near_critical"] == int(((r["flags"] & 1) != 0).sum())
 
 
-def test_alone_equals_in_batch_bitwise(vrt, ctx):
+def alone_case(name):
+    if name == "gaussian":
+        return workloads.gaussian_cube(n_rays=3000)
+    if name == "grid":  # marched from the entry kernel's stored states
+        return (workloads.grid_medium(workloads.noise_grid(48, 3)),
+                workloads.face_cone_rays(3000, 103, 30.0), workloads.trace_params(5e-4, 60000))
+    return (workloads.zernike_lens(), workloads.zernike_rays(3000, seed=900),
+            workloads.trace_params(1e-3, 100000))
+
+
+@pytest.mark.parametrize("name", ["gaussian", "grid", "zernike"])
+def test_alone_equals_in_batch_bitwise(vrt, ctx, name):
     """A ray's result does not depend on which lane, wave or batch runs it, nor
     on when its lane picks it from the queue: the batch runs on one block of
     256 lanes (max_lanes) so that every lane marches about 12 rays in turn, and
-    on 8 blocks with the rays shuffled; both equal the rays run alone."""
-    spec, (P0, d0), prm = workloads.gaussian_cube(n_rays=3000)
+    on 8 blocks with the rays shuffled; both equal the rays run alone (batches
+    of 4 and of 3,000 rays, neither a multiple of the 256-ray blocks)."""
+    spec, (P0, d0), prm = alone_case(name)
     full = run_gpu(vrt, ctx, spec, (P0, d0), dict(prm, max_lanes=256), "fp32c")
     idx = np.array([0, 17, 1234, 2999])
     alone = run_gpu(vrt, ctx, spec, (P0[idx], d0[idx]), prm, "fp32c")
