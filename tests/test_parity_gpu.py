@@ -526,3 +526,49 @@ def test_api_errors(vrt, ctx):
     with pytest.raises(vrt.VrtError):
         vrt.Medium(ctx, workloads.grid_medium(-np.ones((3, 3, 3), np.float32)))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", ["grid", "gaussian"])
+def test_large_batch_beyond_32_bit_byte_offsets(vrt, ctx, name):
+    """A batch of 2^27 + 12,345 rays: the grid march's 80-byte entry states
+    span 10.7 GB and the output arrays 4.3 GB, so byte offsets past 4 GiB are
+    exercised (the Gaussian march enters its rays inline).  Launch points on a
+    regular lattice of the face z = 0 (built on the device), 6 moves each;
+    4,096 sampled rays, the last ones included, equal the same rays traced in
+    a batch of their own, bitwise."""
+    import torch
+
+    free, _ = torch.cuda.mem_get_info()
+    if free < (48 << 30):
+        pytest.skip("needs 48 GB of free device memory")
+    n = (1 << 27) + 12345
+    spec = (workloads.grid_medium(workloads.noise_grid(16, 9)) if name == "grid"
+            else workloads.gaussian_medium())
+    prm = workloads.trace_params(1e-3, 6)
+    k = torch.arange(n, device="cuda", dtype=torch.int64)
+    side = 16381
+    P0 = torch.stack([((k % side).float() + 0.5) / side, (((k // side) % side).float() + 0.5) / side,
+                      torch.zeros(n, device="cuda")], dim=1)
+    d = torch.tensor([0.1, 0.05, 1.0], device="cuda")
+    d0 = (d / d.norm()).expand(n, 3).contiguous()
+    med = vrt.Medium(ctx, spec)
+    try:
+        b = vrt.RayBatch(P0, d0, "fp32c")
+        vrt.trace(med, b, prm, "fp32c")
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(12)
+        idx = np.unique(np.concatenate([rng.integers(0, n, 4000), np.arange(n - 96, n)]))
+        ti = torch.as_tensor(idx, device="cuda")
+        big = {"P": b.out[0:3][:, ti].T.double().cpu().numpy(), "D": b.out[3:6][:, ti].T.double().cpu().numpy(),
+               "u": b.u32[:, ti].cpu().numpy().view("uint32")}
+        assert np.all(big["u"][1] > 0)  # every sampled ray was marched
+        del b
+        small = vrt.RayBatch(P0[ti], d0[ti], "fp32c")
+        vrt.trace(med, small, prm, "fp32c")
+        torch.cuda.synchronize()
+        r = small.results()
+    finally:
+        med.close()
+    assert np.array_equal(big["P"], r["P"]) and np.array_equal(big["D"], r["D"])
+    for i, key in enumerate(("status", "steps", "ntir", "nbtir", "flags")):
+        assert np.array_equal(big["u"][i], r[key]), key
