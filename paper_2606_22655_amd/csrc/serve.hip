@@ -90,8 +90,9 @@ constexpr double kSliceSec = 0.025;     // a class's run yields after this when 
 // One persistent kernel per medium kind: each is the batch kernel's march of
 // its kind wrapped in the job claiming and accounting, compiled for the
 // occupancy its registers allow (analytic media at 3 blocks per CU, grids and
-// the Zernike lens, whose marches need ~215 VGPRs, at 2).  One kind's kernel is
-// resident at a time; the kinds with admitted jobs take turns.
+// the Zernike lens, whose marches with the entry inline need 190-215 VGPRs, at
+// 2).  One kind's kernel is resident at a time; the kinds with admitted jobs
+// take turns.
 constexpr int kClasses = VRT_MEDIUM_ZERNIKE + 1;
 __host__ __device__ constexpr int medium_class(int kind) { return kind; }
 __host__ __device__ constexpr int class_occupancy(int kind) {
