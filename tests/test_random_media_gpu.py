@@ -4,9 +4,12 @@ fiber, homogeneous), its parameters, an enclosing surface (box, sphere,
 z-cylinder) and rays launched from outside towards points inside, so that
 entry refraction, reflection at entry, interior Snell/TIR, boundary TIR and
 exit refraction all occur across the cases.  The bar is the one every march
-parity test uses; in single precision the rays whose oracle result moves by
-1e-5 under a 1e-7 shift of the launch point or turn of its direction are set
-aside (counted, at most 10 %)."""
+parity test uses.  Set aside (counted): rays whose own oracle result moves
+beyond the bar (events, or the exit by more than 1e-4) under a perturbation
+of the launch point and direction the size of the march's rounding -- 1e-12
+for the FP64 march (its exp and the host's differ by an ulp; only rays
+trapped in a box by repeated TIR are that sensitive), 1e-7 for the FP32
+march (at most 3 % of the rays of an analytic medium, 1 % of a grid's)."""
 import math
 
 import numpy as np
@@ -16,7 +19,7 @@ from parity import assert_parity, compare, exempt, ill_conditioned
 
 pytestmark = pytest.mark.gpu
 
-N_CASES = 12
+N_CASES = 24
 
 
 @pytest.fixture(scope="module")
@@ -112,7 +115,15 @@ def test_random_medium_parity(vrt, ctx, orc, seed):
             torch.cuda.synchronize()
             g = b.results()
             if precision == "fp64":
-                rep = compare(o, g, aperture=2.0 * size, spec=spec)
+                # the FP64 march's exp and the host's differ by an ulp: rays
+                # trapped by repeated TIR can amplify that to the bar, so the
+                # rays whose own oracle result moves beyond it under a 1e-12
+                # launch perturbation are set aside (none but in trapping boxes)
+                bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-12, tol=1e-4,
+                                      turn=1e-12)
+                assert bad.sum() <= 0.01 * len(bad)
+                rep = compare(exempt(o, bad), exempt(g, bad), aperture=2.0 * size, spec=spec)
+                rep["ill_conditioned"] = int(bad.sum())
             else:
                 # rays whose own oracle events change, or whose oracle result
                 # moves by more than the bar, under a float32-sized launch
@@ -136,9 +147,10 @@ def test_random_medium_parity(vrt, ctx, orc, seed):
 # index 1 or 1.33.  FP64: the oracle's decisions on whole paths (entry,
 # interior and boundary TIR, exits).  FP32: per ray over the first 128 moves,
 # as for the 256^3 grid (these grids are chaotic over whole paths), rays whose
-# oracle state moves under a 1e-9 launch shift set aside (at most 1 %).
+# oracle result moves beyond the bar under a 1e-7 shift and turn of the launch
+# set aside (at most 1 %).
 # ---------------------------------------------------------------------------
-N_GRID_CASES = 8
+N_GRID_CASES = 16
 
 
 def grid_case(seed):
@@ -189,7 +201,11 @@ def test_random_grid_parity(vrt, ctx, orc, seed):
                 assert np.abs(o["P"] - g["P"]).max() < 1e-9
                 assert np.abs(o["D"] - g["D"]).max() < 1e-9
             else:
-                bad = ill_conditioned(orc.trace, spec, rays, prm)
+                # the float32-sized probe of the analytic media (1e-7 shift and
+                # turn): coarse quantized grids hold rays that a 1e-8
+                # perturbation already moves past the bar within 128 moves
+                bad = ill_conditioned(orc.trace, spec, rays, prm, delta=1e-7, tol=1e-4,
+                                      turn=1e-7)
                 assert bad.sum() <= 0.01 * len(bad)
                 rep = compare(exempt(o, bad), exempt(g, bad), aperture=2.0 * size, spec=spec)
                 rep["ill_conditioned"] = int(bad.sum())
