@@ -256,6 +256,28 @@ def test_served_random_grids_equal_batch(vrt, ctx):
             m.close()
 
 
+def test_served_random_media_equal_batch(vrt, ctx):
+    """Jobs on twelve seeded random analytic media (five kinds, three
+    surfaces, ambient index 1 or 1.33) served together: every ray equals the
+    batch trace of the same rays, bitwise, over whole paths."""
+    from test_random_media_gpu import case, outside_rays
+
+    cases = [case(seed) for seed in range(12)]
+    meds = [vrt.Medium(ctx, spec) for spec, _ in cases]
+    try:
+        prm = {"dL0": 2e-3, "max_steps": 20000, "crit_rad": 1e-6, "tie_eps": 1e-7}
+        jobs = [(mi, outside_rays(800, 300 + mi, size), prm) for mi, (_, size) in enumerate(cases)]
+        res, _, _ = serve_all(vrt, ctx, meds, jobs)
+        for (mi, rays, _), r in zip(jobs, res):
+            ref = batch_trace(vrt, ctx, meds[mi], rays, prm)
+            diff = [k for k in ("P", "D", "status", "steps", "ntir", "nbtir", "flags")
+                    if not np.array_equal(ref[k], r[k])]
+            assert not diff, (cases[mi][0]["kind"], cases[mi][0]["boundary"]["kind"], diff)
+    finally:
+        for m in meds:
+            m.close()
+
+
 def test_served_grid_jobs_first_128_moves(vrt, ctx, orc):
     """Grid jobs served on a 48^3 and a 256^3 quantized grid, truncated after
     128 moves, against the oracle per ray under the pass rule (the grid is
