@@ -58,8 +58,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("march_fp32c.hip", "lane32.h", "media.h", "vrt_common.h", "dispatch.h")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {  # workload -> (fetch KiB, write KiB, kernel code sha256); profiles/march_fp32c_hbm_traffic.md
-    "freeform": (80267.1, 297006.9, "b786c5200aa8cce6b5cf8939c6cb2df0cc9edb42560c6aabb92aea15e2220013"),
-    "grid": (427678788.5, 1578010.4, "b786c5200aa8cce6b5cf8939c6cb2df0cc9edb42560c6aabb92aea15e2220013"),
+    "freeform": (79294.8, 310745.0, "a4d38d1598657f35940edbfac111fe6ef8d98c823000523bbb3da4974dd4d666"),
+    "grid": (427682086.25, 1578027.75, "a4d38d1598657f35940edbfac111fe6ef8d98c823000523bbb3da4974dd4d666"),
 }
 
 

@@ -60,6 +60,24 @@ __device__ __forceinline__ void split(double v, float &h, float &c) {
     h = (float)v;
     c = (float)((double)h - v);
 }
+// The tangential rule's new direction R = (w I + a N) / |w I + a N|,
+// w = sqrt(1 - a^2), Eqs. (16)-(18), as the increment R - I.  With
+// c = N.I (|c| <= eps_tan), |w I + a N|^2 = 1 + 2 a w c = L^2, and
+// R - I = (k I + a N) / L with k = w - L = -(a^2 + 2 a w c) / (w + L), formed
+// without cancellation; at c = 0, L = 1 and k = -a^2 / (1 + w).
+__device__ __forceinline__ void tangent_increment(float a, float c, float Ix, float Iy, float Iz,
+                                                  float Nx, float Ny, float Nz, float &incx,
+                                                  float &incy, float &incz) {
+    const float w = fsqrt(fmaxf(0.0f, 1.0f - a * a));
+    const float x = 2.0f * a * w * c;
+    const float L = fsqrt(1.0f + x);
+    const float k = -(a * a + x) / (w + L);
+    const float il = frcp(L);
+    incx = (k * Ix + a * Nx) * il;
+    incy = (k * Iy + a * Ny) * il;
+    incz = (k * Iz + a * Nz) * il;
+}
+
 // Step length Delta = (dh + dl) / (nh + nl) as Dh + Dl (the low parts are
 // far below the high ones): a quotient from the hardware reciprocal, its
 // exact residual dh - q nh (fma), the low parts' first-order terms, and one
@@ -417,12 +435,8 @@ __device__ __forceinline__ void grid_decide(const MediumDev &m, const float4 *__
             const d3 Q = mk((double)L.Phx - L.Pcx + D64 * Nx, (double)L.Phy - L.Pcy + D64 * Ny,
                             (double)L.Phz - L.Pcz + D64 * Nz);
             const float dnp = (float)(grid_index64(m, Q) - ((double)nb + (double)delta));
-            const float a = dnp * frcp(2.0f * ni);
-            const float w = fsqrt(fmaxf(0.0f, 1.0f - a * a));
-            const float k = -a * a / (1.0f + w);  // sqrt(1-a^2) - 1 without cancellation
-            incx = k * L.Ihx + a * Nx;
-            incy = k * L.Ihy + a * Ny;
-            incz = k * L.Ihz + a * Nz;
+            tangent_increment(dnp * frcp(2.0f * ni), c, L.Ihx, L.Ihy, L.Ihz, Nx, Ny, Nz, incx, incy,
+                              incz);
             L.flags |= VRT_FLAG_TANGENT;
         } else {
             const float m1 = -dn * frcp(ni);  // mu_i - 1, mu_i = n_{i-1} / n_i
@@ -532,12 +546,8 @@ __device__ __forceinline__ bool lane_step(const MediumDev &m, const MedF &mf, Bu
                     med32<MK>(m, mf, bumps, dL0, mkf(L.Phx + qx, L.Phy + qy, L.Phz + qz), mkf(qx, qy, qz), ni,
                               np, npl, gp, dnp);
                 }
-                const float a = dnp * frcp(2.0f * ni);
-                const float w = fsqrt(fmaxf(0.0f, 1.0f - a * a));
-                const float k = -a * a / (1.0f + w);  // sqrt(1-a^2) - 1 without cancellation
-                incx = k * L.Ihx + a * Nx;
-                incy = k * L.Ihy + a * Ny;
-                incz = k * L.Ihz + a * Nz;
+                tangent_increment(dnp * frcp(2.0f * ni), c, L.Ihx, L.Ihy, L.Ihz, Nx, Ny, Nz, incx,
+                                  incy, incz);
                 L.flags |= VRT_FLAG_TANGENT;
             } else {
                 const float m1 = -dn * frcp(ni);  // mu_i - 1, mu_i = n_{i-1} / n_i

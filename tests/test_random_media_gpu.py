@@ -216,3 +216,49 @@ def test_random_grid_parity(vrt, ctx, orc, seed):
             assert_parity(rep)
     finally:
         med.close()
+
+
+@pytest.mark.parametrize("eps_tan", [1e-3, 3e-2])
+def test_tangential_threshold_on_random_media(vrt, ctx, orc, eps_tan):
+    """The tangential rule (case (iv), Eqs. (16)-(18)) taken whenever
+    |N.I| <= eps_tan, on six random analytic media and two random grids:
+    with eps_tan = 3e-2 nearly every ray takes it, many times.  Both
+    precisions against the oracle under the bar and the set-asides above (the
+    grids' FP32 march over 128 moves)."""
+    import torch
+
+    for seed in list(range(6)) + ["g0", "g1"]:
+        if isinstance(seed, str):
+            spec, size, _ = grid_case(int(seed[1:]))
+            rs = 400 + int(seed[1:])
+        else:
+            spec, size = case(seed)
+            rs = 500 + seed
+        rays = outside_rays(500, rs, size)
+        full = {"dL0": 2e-3, "max_steps": 20000, "crit_rad": 1e-6, "tie_eps": 1e-7,
+                "eps_tan": eps_tan}
+        taken = 0
+        med = vrt.Medium(ctx, spec)
+        try:
+            for precision in ("fp64", "fp32c"):
+                prm = dict(full, max_steps=128) if (precision == "fp32c" and
+                                                    spec["kind"] == "grid") else full
+                o = orc.trace(spec, rays, prm)
+                taken = max(taken, int(((o["flags"] & 2) != 0).sum()))
+                b = vrt.RayBatch(rays[0], rays[1], precision)
+                vrt.trace(med, b, prm, precision)
+                torch.cuda.synchronize()
+                g = b.results()
+                d = 1e-12 if precision == "fp64" else 1e-7
+                bad = ill_conditioned(orc.trace, spec, rays, prm, delta=d, tol=1e-4, turn=d)
+                assert bad.sum() <= 0.03 * len(bad)
+                rep = compare(exempt(o, bad), exempt(g, bad), aperture=2.0 * size, spec=spec)
+                print(f"\n[tangent eps {eps_tan} {seed} {spec['kind']} {precision}] rays taking "
+                      f"the rule {int(((o['flags'] & 2) != 0).sum())} set aside {int(bad.sum())} "
+                      f"pos_err_max {rep['pos_err_max']:.2e} dir_err_max {rep['dir_err_max']:.2e} "
+                      f"fail {rep['fail']}", flush=True)
+                assert_parity(rep)
+        finally:
+            med.close()
+        if spec["kind"] != "homogeneous":
+            assert taken > 0
