@@ -262,3 +262,58 @@ def test_tangential_threshold_on_random_media(vrt, ctx, orc, eps_tan):
             med.close()
         if spec["kind"] != "homogeneous":
             assert taken > 0
+
+
+def test_random_trace_parameters(vrt, ctx, orc):
+    """Seeded random trace parameters on the random media and grids above:
+    dL0 log-uniform in [5e-4, 2e-2], max_steps in [50, 20000], an exit plane
+    on half of the trials.  Both precisions against the oracle under the bar
+    and the set-asides above (at most 10 % of a trial's rays -- long marches
+    in the trapping boxes -- and 3 % over all); a single-precision trace whose dL0 exceeds the
+    medium's limit must be refused (EINVAL) before any launch."""
+    import torch
+
+    rng = np.random.default_rng(2468)
+    refused = set_aside = compared = 0
+    for trial in range(24):
+        which = int(rng.integers(0, 16))
+        if which < 12:
+            spec, size = case(which)
+        else:
+            spec, size, _ = grid_case(which - 12)
+        dL0 = float(math.exp(rng.uniform(math.log(5e-4), math.log(2e-2))))
+        ms = int(rng.integers(50, 20000))
+        plane = float(rng.uniform(1.0, 3.0) * size) if rng.random() < 0.5 else None
+        prm = {"dL0": dL0, "max_steps": ms, "crit_rad": 1e-6, "tie_eps": 1e-7}
+        if plane is not None:
+            prm["exit_plane_z"] = plane
+        rays = outside_rays(400, 700 + trial, size)
+        med = vrt.Medium(ctx, spec)
+        try:
+            for precision in ("fp64", "fp32c"):
+                p2 = (dict(prm, max_steps=min(ms, 128))
+                      if precision == "fp32c" and spec["kind"] == "grid" else prm)
+                b = vrt.RayBatch(rays[0], rays[1], precision)
+                try:
+                    vrt.trace(med, b, p2, precision)
+                except vrt.VrtError as e:
+                    assert precision == "fp32c" and "exceeds" in str(e), str(e)
+                    refused += 1
+                    continue
+                torch.cuda.synchronize()
+                g = b.results()
+                o = orc.trace(spec, rays, p2)
+                d = 1e-12 if precision == "fp64" else 1e-7
+                bad = ill_conditioned(orc.trace, spec, rays, p2, delta=d, tol=1e-4, turn=d)
+                # long marches in the trapping boxes hold more chaotic rays
+                assert bad.sum() <= 0.10 * len(bad)
+                set_aside += int(bad.sum())
+                compared += len(bad)
+                rep = compare(exempt(o, bad), exempt(g, bad), aperture=2.0 * size, spec=spec)
+                assert_parity(rep)
+        finally:
+            med.close()
+    print(f"\n[random parameters] 24 trials, {refused} single-precision traces refused "
+          f"(dL0 beyond the medium's limit), {set_aside} of {compared} rays set aside",
+          flush=True)
+    assert set_aside <= 0.03 * compared
