@@ -278,6 +278,39 @@ def test_served_random_media_equal_batch(vrt, ctx):
             m.close()
 
 
+def test_served_random_parameters_equal_batch(vrt, ctx):
+    """Sixteen jobs on six seeded random media (two of them grids), each with
+    its own random trace parameters (dL0, step cap, exit plane, tangential
+    threshold), so that jobs on one medium fall into several groups: served
+    together, every ray equals the batch trace of the same rays, bitwise."""
+    import math
+
+    from test_random_media_gpu import case, grid_case, outside_rays
+
+    cases = [case(s) for s in (0, 1, 2, 3)] + [grid_case(s)[:2] for s in (1, 2)]
+    meds = [vrt.Medium(ctx, spec) for spec, _ in cases]
+    rng = np.random.default_rng(97)
+    try:
+        jobs = []
+        for j in range(16):
+            mi = int(rng.integers(0, len(cases)))
+            size = cases[mi][1]
+            prm = {"dL0": float(math.exp(rng.uniform(math.log(5e-4), math.log(5e-3)))),
+                   "max_steps": int(rng.integers(50, 20000)), "crit_rad": 1e-6, "tie_eps": 1e-7,
+                   "eps_tan": float(rng.choice([0.0, 3e-2]))}
+            if rng.random() < 0.5:
+                prm["exit_plane_z"] = float(rng.uniform(1.0, 3.0) * size)
+            jobs.append((mi, outside_rays(int(rng.integers(100, 1500)), 900 + j, size), prm))
+        res, infos, _ = serve_all(vrt, ctx, meds, jobs)
+        for (mi, rays, prm), r, i in zip(jobs, res, infos):
+            assert i["state"] == "DONE" and i["error"] == 0
+            ref = batch_trace(vrt, ctx, meds[mi], rays, prm)
+            assert same(ref, r), (cases[mi][0]["kind"], prm)
+    finally:
+        for m in meds:
+            m.close()
+
+
 def test_served_grid_jobs_first_128_moves(vrt, ctx, orc):
     """Grid jobs served on a 48^3 and a 256^3 quantized grid, truncated after
     128 moves, against the oracle per ray under the pass rule (the grid is
