@@ -22,7 +22,10 @@ follow: "freeform" (the 16-Gaussian-bump cube, 1,048,576 rays, 20 deg cone,
 with per-ray parity of 524,288 rays against the oracle) and "served" (a
 Poisson stream of 120 jobs at 80 % of the measured capacity over eight
 resident media, its rays/s and p50/p99 latency next to one plain FP64 launch
-per job, and the parity of sampled served rays).
+per job, and the parity of sampled served rays).  The grid and freeform
+records also carry "two_in_flight": the rate of a stream of batches traced
+two at a time on two streams, so that the last long rays of one trace share
+the device with the start of the next (reported beside value, never as it).
 
 Prints one JSON line.
 """
@@ -794,6 +797,29 @@ def grid_parity(vrt, torch, med, spec, rays, prm, g_full, oracle_full, idx_full,
     return {"first_128_moves": first, "full_path_statistics": st}
 
 
+def two_in_flight(vrt, torch, med, batch, rays, prm, precision, steps, g_res):
+    """A stream of batches with two in flight: consecutive traces of two
+    resident batches alternate over two streams, so that the last long rays of
+    one trace share the device with the start of the next.  Reported beside
+    value (one trace at a time), never as it; the second batch's results must
+    equal the first's bitwise."""
+    other = vrt.RayBatch(rays[0], rays[1], precision)
+    pair = (batch, other)
+    streams = (torch.cuda.Stream(), torch.cuda.Stream())
+    for q in range(2):
+        vrt.trace(med, pair[q], prm, precision, stream=streams[q].cuda_stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        vrt.trace(med, pair[k % 2], prm, precision, stream=streams[k % 2].cuda_stream)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / steps
+    r2 = other.results()
+    same = all(np.array_equal(g_res[key], r2[key]) for key in g_res)
+    del other
+    return per, same
+
+
 def batch_record(vrt, torch, ctx, name, args, cpu=True):
     """One batch workload: timed traces, roofline, FP64 GPU march, the oracle's
     rate on a sample of the same rays and the parity of the timed results."""
@@ -816,6 +842,17 @@ def batch_record(vrt, torch, ctx, name, args, cpu=True):
                     "on one stream; not value"}
     print(f"[bench] {name}: {args.steps} traces, {ms:.3f} ms each, {value:.4g} ray-steps/s",
           file=sys.stderr, flush=True)
+    overlap = None
+    if args.two_in_flight:
+        per2, same2 = two_in_flight(vrt, torch, med, batch, rays, prm, precision, args.steps,
+                                    g_res)
+        overlap = {"ray_steps_per_s": ray_steps / per2, "ms_per_step": round(per2 * 1e3, 3),
+                   "gain": round(ms / 1e3 / per2, 3), "bitwise_equal": bool(same2),
+                   "note": "two resident batches traced alternately on two streams, host clock "
+                           "around the traces; a stream of batches, not value"}
+        print(f"[bench] {name}: two in flight {per2 * 1e3:.3f} ms per trace "
+              f"({ray_steps / per2:.4g} ray-steps/s), bitwise equal {same2}",
+              file=sys.stderr, flush=True)
     fp64_gpu = None
     if not args.no_fp64_gpu and precision != "fp64":
         b64 = vrt.RayBatch(rays[0], rays[1], "fp64")
@@ -857,6 +894,8 @@ def batch_record(vrt, torch, ctx, name, args, cpu=True):
                       "dL0": prm["dL0"], "max_steps": prm["max_steps"]},
            "wall_s": round(wall, 3), "roofline": roof, "counters": cnt,
            "pcie_inclusive": pcie}
+    if overlap:
+        rec["two_in_flight"] = overlap
     if fp64_gpu:
         rec["fp64_gpu_march"] = fp64_gpu
     if cpu and not args.no_cpu_baseline:
@@ -904,6 +943,9 @@ def main(argv=None):
                     help="rays of the oracle sample (default: about 10-30 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-gpu", action="store_true")
+    ap.add_argument("--two-in-flight", action="store_true",
+                    help="single workloads: add the record of two batches in flight (the "
+                         "headline run always has it)")
     ap.add_argument("--no-served", action="store_true", help="headline: skip the served record")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -941,9 +983,11 @@ def main(argv=None):
     # mix as sub-records
     grid_args = argparse.Namespace(**vars(args))
     grid_args.rays = None
+    grid_args.two_in_flight = True
     out = header(args, batch_record(vrt, torch, ctx, "grid", grid_args))
     ff_args = argparse.Namespace(**vars(args))
     ff_args.rays = None
+    ff_args.two_in_flight = True
     out["freeform"] = batch_record(vrt, torch, ctx, "freeform", ff_args)
     ctx.close()
     if not args.no_served:
