@@ -61,8 +61,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("march_fp32c.hip", "lane32.h", "media.h", "vrt_common.h", "dispatch.h")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {  # workload -> (fetch KiB, write KiB, kernel code sha256); profiles/march_fp32c_hbm_traffic.md
-    "freeform": (79294.8, 310745.0, "a4d38d1598657f35940edbfac111fe6ef8d98c823000523bbb3da4974dd4d666"),
-    "grid": (427682086.25, 1578027.75, "a4d38d1598657f35940edbfac111fe6ef8d98c823000523bbb3da4974dd4d666"),
+    "freeform": (79289.96, 304980.59, "22def1ced10ae8adc33b958dea059916a7dafc3a2e08f57ed3de6e4cc4d39406"),
+    "grid": (427689715.39, 1578064.37, "22def1ced10ae8adc33b958dea059916a7dafc3a2e08f57ed3de6e4cc4d39406"),
 }
 
 

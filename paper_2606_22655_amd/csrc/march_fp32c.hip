@@ -71,6 +71,16 @@ __global__ __launch_bounds__(256, (march_occupancy<MK, kPre>())) void march_fp32
     // Waves are always full (256-lane blocks), so a lane needs a ray iff its
     // bit is in neither mask.
     uint64_t act = 0, done_m = 0;
+    // Media evaluated in double end their traces with a few rays trapped
+    // along a wall, each a long dependent chain of FP64 work per step: a wave
+    // that holds a ray past a sixth of the step cap raises its issue priority,
+    // so that such rays advance while the device is still full instead of
+    // alone at the end.  (The other media gain nothing from it: their long
+    // rays are short chains, and the per-step test costs them ~2 %.)
+    const uint32_t long_steps =
+        (uint32_t)(t.max_steps / 6 > 1024 ? (t.max_steps / 6 < 0x7FFFFFFF ? t.max_steps / 6 : 0x7FFFFFFF)
+                                          : 1024);
+    bool raised = false;
     for (;;) {
         const uint64_t nm = ~(act | done_m);
         if (nm) {  // refill idle lanes from the queue with one atomic per wave
@@ -99,6 +109,14 @@ __global__ __launch_bounds__(256, (march_occupancy<MK, kPre>())) void march_fp32
         if (active) active = lane_step<MK>(m, mf, bumps, rec, b, t, io, L, gc, dL0, eps_tan, mrg,
                                            crit_f);
         act = __ballot(active);
+        if constexpr (kIndexIn64<MK>) {
+            const bool hold_long = __ballot(active && L.steps > long_steps) != 0;
+            if (hold_long != raised) {
+                if (hold_long) __builtin_amdgcn_s_setprio(3);
+                else __builtin_amdgcn_s_setprio(0);
+                raised = hold_long;
+            }
+        }
     }
 }
 
