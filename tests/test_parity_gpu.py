@@ -400,17 +400,25 @@ def alone_case(name):
     if name == "grid":  # marched from the entry kernel's stored states
         return (workloads.grid_medium(workloads.noise_grid(48, 3)),
                 workloads.face_cone_rays(3000, 103, 30.0), workloads.trace_params(5e-4, 60000))
+    if name == "spherical":
+        return (workloads.spherical_medium(), workloads.sphere_aimed_rays(3000, seed=901),
+                workloads.trace_params(1e-3, 20000))
+    # a step cap of 6,144 puts the raised issue priority of waves holding a
+    # ray past a sixth of the cap (1,024 steps) on and off in most waves
+    cap = 6144 if name == "zernike_low_cap" else 100000
     return (workloads.zernike_lens(), workloads.zernike_rays(3000, seed=900),
-            workloads.trace_params(1e-3, 100000))
+            workloads.trace_params(1e-3, cap))
 
 
-@pytest.mark.parametrize("name", ["gaussian", "grid", "zernike"])
+@pytest.mark.parametrize("name", ["gaussian", "grid", "zernike", "zernike_low_cap", "spherical"])
 def test_alone_equals_in_batch_bitwise(vrt, ctx, name):
     """A ray's result does not depend on which lane, wave or batch runs it, nor
     on when its lane picks it from the queue: the batch runs on one block of
     256 lanes (max_lanes) so that every lane marches about 12 rays in turn, and
     on 8 blocks with the rays shuffled; both equal the rays run alone (batches
-    of 4 and of 3,000 rays, neither a multiple of the 256-ray blocks)."""
+    of 4 and of 3,000 rays, neither a multiple of the 256-ray blocks).  For
+    the media evaluated in double the waves also change their issue priority
+    while they hold long rays, which moves rays between lanes in time only."""
     spec, (P0, d0), prm = alone_case(name)
     full = run_gpu(vrt, ctx, spec, (P0, d0), dict(prm, max_lanes=256), "fp32c")
     idx = np.array([0, 17, 1234, 2999])
