@@ -224,7 +224,10 @@ int vrt_medium_device_bytes(vrt_medium_t m, size_t *out);
  * counters, each guarded by an event (a launch waits on its stream for the
  * counter's previous launch); a launch captured in a graph keeps a counter of
  * its own for the context's life (960 of them), so replays never share one
- * with any other launch.
+ * with any other launch.  A trace ends with its longest rays on a nearly
+ * idle device; a caller with a stream of batches keeps two traces in flight
+ * on two streams so that the next one fills it (a ray's result does not
+ * depend on what runs beside it).
  * Device memory: an eager VRT_FP32_COMP launch on a grid or Zernike-lens
  * medium first enters every ray (launch, flight to the enclosing surface,
  * entry refraction) in a kernel of its own and keeps the 80-byte states in
