@@ -505,6 +505,27 @@ def trace(medium, batch, params, precision, stream=None):
     vrt_trace(medium.handle, make_params(params, precision), batch.rays, batch.n, stream)
 
 
+def trace_batches(medium, batches, params, precision, streams=None):
+    """Enqueue the marches of several batches through ``medium``, two at a
+    time: batch k goes to ``streams[k % 2]`` (default: two new streams), so
+    that each trace's last long rays share the device with the next trace's
+    start.  Both streams first wait for torch's current stream (inputs written
+    there are visible), and the current stream then waits for both (results
+    are ready in its order).  Each batch's result is the one ``trace`` gives."""
+    torch = _torch()
+    cur = torch.cuda.current_stream()
+    if streams is None:
+        streams = (torch.cuda.Stream(), torch.cuda.Stream())
+    if len(streams) != 2:
+        raise ValueError("trace_batches: two streams")
+    for s in streams:
+        s.wait_stream(cur)
+    for k, b in enumerate(batches):
+        trace(medium, b, params, precision, stream=streams[k % 2].cuda_stream)
+    for s in streams:
+        cur.wait_stream(s)
+
+
 def trace_paths(medium, batch, params, cap, stream=None):
     """Enqueue the FP64 march of ``batch`` (an fp64 RayBatch) with its
     polylines recorded; returns device tensors ``path`` (cap, n, 3), point k

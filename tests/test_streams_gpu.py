@@ -63,6 +63,37 @@ def test_concurrent_streams_equal_serial(vrt, ctx):
             m.close()
 
 
+def test_trace_batches_two_in_flight_equal_serial(vrt, ctx):
+    """A stream of ragged batches traced two at a time on two streams
+    (trace_batches) gives every batch the result of a serial trace, and the
+    results are in order on torch's current stream: read with no device-wide
+    synchronisation in between."""
+    import torch
+
+    cases = [(workloads.grid_medium(workloads.noise_grid(32, 516)), 30.0, "fp32c"),
+             (workloads.zernike_lens(), None, "fp32c"),
+             (workloads.gaussian_medium(517), 20.0, "fp64")]
+    sizes = (3001, 700, 4096, 257, 1999)
+    for spec, cone, prec in cases:
+        prm = workloads.trace_params(1e-3, 20000)
+        med = vrt.Medium(ctx, spec)
+        try:
+            rays = [workloads.zernike_rays(n, seed=520 + k) if cone is None
+                    else workloads.face_cone_rays(n, 520 + k, cone) for k, n in enumerate(sizes)]
+            serial = []
+            for r in rays:
+                b = vrt.RayBatch(r[0], r[1], prec)
+                vrt.trace(med, b, prm, prec)
+                serial.append(b.results())
+            batches = [vrt.RayBatch(r[0], r[1], prec) for r in rays]
+            vrt.trace_batches(med, batches, prm, prec)
+            for k, b in enumerate(batches):
+                assert same(serial[k], b.results()), (spec["kind"], k)
+        finally:
+            med.close()
+        torch.cuda.synchronize()
+
+
 def test_trace_captured_in_a_graph_replays_the_eager_result(vrt, ctx):
     import torch
 
