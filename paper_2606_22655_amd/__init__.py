@@ -8,7 +8,8 @@ no CPU fallback: if the library has not been built, or no GPU is present,
 the calls raise.
 
 Convenience layer: ``Context``, ``Medium`` (built from the medium dicts of
-``workloads.py``) and ``trace`` (torch tensors in, dict of tensors out).
+``workloads.py``), ``trace`` (torch tensors in, dict of tensors out) and
+``trace_batches`` (a list of batches, two traces in flight on two streams).
 """
 from __future__ import annotations
 
@@ -512,12 +513,12 @@ def trace_batches(medium, batches, params, precision, streams=None):
     start.  Both streams first wait for torch's current stream (inputs written
     there are visible), and the current stream then waits for both (results
     are ready in its order).  Each batch's result is the one ``trace`` gives."""
+    if streams is not None and len(streams) != 2:
+        raise ValueError("trace_batches: two streams")
     torch = _torch()
     cur = torch.cuda.current_stream()
     if streams is None:
         streams = (torch.cuda.Stream(), torch.cuda.Stream())
-    if len(streams) != 2:
-        raise ValueError("trace_batches: two streams")
     for s in streams:
         s.wait_stream(cur)
     for k, b in enumerate(batches):

@@ -115,3 +115,10 @@ def test_missing_library_fails_loudly():
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
                        timeout=300)
     assert r.returncode == 0 and "raised" in r.stdout and "not built" in r.stdout, r.stderr
+
+
+def test_trace_batches_wants_two_streams(vrt):
+    """The binding's two-in-flight helper refuses a stream list of another
+    length before it touches the GPU."""
+    with pytest.raises(ValueError):
+        vrt.trace_batches(None, [], {}, "fp32c", streams=(None,))
