@@ -806,12 +806,10 @@ def two_in_flight(vrt, torch, med, batch, rays, prm, precision, steps, g_res):
     other = vrt.RayBatch(rays[0], rays[1], precision)
     pair = (batch, other)
     streams = (torch.cuda.Stream(), torch.cuda.Stream())
-    for q in range(2):
-        vrt.trace(med, pair[q], prm, precision, stream=streams[q].cuda_stream)
+    vrt.trace_batches(med, pair, prm, precision, streams=streams)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(steps):
-        vrt.trace(med, pair[k % 2], prm, precision, stream=streams[k % 2].cuda_stream)
+    vrt.trace_batches(med, [pair[k % 2] for k in range(steps)], prm, precision, streams=streams)
     torch.cuda.synchronize()
     per = (time.perf_counter() - t0) / steps
     r2 = other.results()
